@@ -1,0 +1,371 @@
+/*
+ * abacus_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded FP64 reference for the near-field force of the
+ * Abacus method (Garrison et al. 2021, "The Abacus Cosmological N-body Code").
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * this file's library; the product path never does.  It shares no code, header,
+ * table or constant with the HIP implementation.
+ *
+ * What it computes (each function cites the passage it follows):
+ *   oracle_bin     cell assignment, cell-relative offsets and a stable counting
+ *                  sort by cell (Sec. 2.2 grid of K^3 cells; Sec. 3.5.1
+ *                  positions stored as offsets from cell centres).
+ *   oracle_forces  the near-field acceleration of selected sinks: a direct sum
+ *                  over every particle in the (2R+1)^3 cells around the sink's
+ *                  cell (Sec. 3.4.1), open boundary conditions on the periodic
+ *                  image that lies in the neighbouring cell (Sec. 3.4.2), with
+ *                  the spline-softened force of Eq. 3 and eps_s = 2.16 eps_p
+ *                  (Sec. 3.2).
+ *   oracle_vjp     the vector-Jacobian product of those accelerations with a
+ *                  cotangent, binning frozen (derived from Eq. 3).
+ *   oracle_fd      a central finite difference of the same loss (binning
+ *                  frozen), used to pin oracle_vjp.
+ *
+ * Readings of the paper taken here (Eq. 3 gives F(r) with no sign, G or mass):
+ *   - attractive force, d = x_j - x_i, G*m = 1 for every particle;
+ *   - a particle never acts on itself; coincident particles (r = 0) give 0;
+ *   - near-field membership is by periodic cell offset in [-R, R]^3 (Chebyshev
+ *     distance in cells), K >= 2R+1 required;
+ *   - positions with |x*K/L| >= 2^30 or non-finite are rejected.
+ *
+ * Build: cc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so every
+ * product and sum below is one IEEE operation).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+#define ORACLE_EPOS (-5)
+
+/* The spline softening length is 2.16 times the Plummer-equivalent length
+ * (Sec. 3.2, same minimum pairwise orbital time). */
+static const double SPLINE_OVER_PLUMMER = 2.16;
+
+/* ------------------------------------------------------------------------- */
+/* Cell assignment (Sec. 2.2, Sec. 3.5.1).                                     */
+/* t = x * (K/L) in cell units; the unwrapped cell is floor(t); its periodic   */
+/* index is that floor mod K; the offset from the cell centre is               */
+/* t - (floor(t) + 1/2), rounded once to FP32.                                 */
+/* ------------------------------------------------------------------------- */
+static int cell_coord(float x, double cells_per_len, int64_t K, int64_t *unwrapped,
+                      int64_t *wrapped, float *offset)
+{
+    double t = (double)x * cells_per_len;
+    if (!isfinite(t) || fabs(t) >= 1073741824.0) return ORACLE_EPOS;
+    double fl = floor(t);
+    int64_t cu = (int64_t)fl;
+    int64_t c = cu % K;
+    if (c < 0) c += K;
+    *unwrapped = cu;
+    *wrapped = c;
+    *offset = (float)(t - (fl + 0.5));
+    return ORACLE_OK;
+}
+
+static int check_box(double L, int32_t K, int32_t R, double eps_p)
+{
+    if (!(L > 0.0) || !isfinite(L)) return ORACLE_EINVAL;
+    if (R < 0 || K < 2 * R + 1) return ORACLE_EINVAL;
+    if (!(eps_p > 0.0) || !isfinite(eps_p)) return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* Per-particle unwrapped and wrapped cell coordinates plus the linear cell id
+ * (x slowest, z fastest: slabs along x, pencils along z). */
+typedef struct {
+    int64_t n, K;
+    int64_t *cu;     /* n x 3 unwrapped cell coordinates */
+    int32_t *cell;   /* n linear cell ids */
+    int32_t *start;  /* K^3 + 1 offsets into order[] */
+    int32_t *order;  /* n particle indices sorted by cell, stable */
+} grid_t;
+
+static void grid_free(grid_t *g)
+{
+    free(g->cu); free(g->cell); free(g->start); free(g->order);
+    memset(g, 0, sizeof(*g));
+}
+
+static int grid_build(grid_t *g, int64_t n, const float *pos, double L, int64_t K,
+                      float *rel /* optional n x 4 */)
+{
+    memset(g, 0, sizeof(*g));
+    g->n = n; g->K = K;
+    int64_t ncell = K * K * K;
+    g->cu = (int64_t *)malloc(sizeof(int64_t) * (size_t)(3 * (n > 0 ? n : 1)));
+    g->cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    g->start = (int32_t *)calloc((size_t)(ncell + 1), sizeof(int32_t));
+    g->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!g->cu || !g->cell || !g->start || !g->order) { grid_free(g); return ORACLE_ENOMEM; }
+    double s = (double)K / L;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            float off;
+            int rc = cell_coord(pos[3 * i + a], s, K, &g->cu[3 * i + a], &c[a], &off);
+            if (rc) { grid_free(g); return rc; }
+            if (rel) rel[4 * i + a] = off;
+        }
+        if (rel) rel[4 * i + 3] = 0.0f;
+        g->cell[i] = (int32_t)((c[0] * K + c[1]) * K + c[2]);
+    }
+    /* counting sort: counts, exclusive prefix sum, placement in index order */
+    for (int64_t i = 0; i < n; ++i) g->start[g->cell[i] + 1] += 1;
+    for (int64_t c = 0; c < ncell; ++c) g->start[c + 1] += g->start[c];
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)ncell);
+    if (!fill) { grid_free(g); return ORACLE_ENOMEM; }
+    memcpy(fill, g->start, sizeof(int32_t) * (size_t)ncell);
+    for (int64_t i = 0; i < n; ++i) g->order[fill[g->cell[i]]++] = (int32_t)i;
+    free(fill);
+    return ORACLE_OK;
+}
+
+/*
+ * oracle_bin: cell ids, cell offsets (K^3+1), the sorted order (slot -> original
+ * index, ascending original index inside a cell) and the FP32 cell-relative
+ * coordinates in sorted order (n x 4, 4th component 0).
+ */
+int oracle_bin(int64_t n, const float *pos, double L, int32_t K, int32_t *cell_out,
+               int32_t *offsets_out, int32_t *perm_out, float *rel_out)
+{
+    if (n < 0 || (n > 0 && !pos) || !(L > 0.0) || !isfinite(L) || K < 1) return ORACLE_EINVAL;
+    float *rel = (float *)malloc(sizeof(float) * (size_t)(4 * (n > 0 ? n : 1)));
+    if (!rel) return ORACLE_ENOMEM;
+    grid_t g;
+    int rc = grid_build(&g, n, pos, L, K, rel);
+    if (rc) { free(rel); return rc; }
+    int64_t ncell = (int64_t)K * K * K;
+    if (cell_out) memcpy(cell_out, g.cell, sizeof(int32_t) * (size_t)n);
+    if (offsets_out) memcpy(offsets_out, g.start, sizeof(int32_t) * (size_t)(ncell + 1));
+    if (perm_out) memcpy(perm_out, g.order, sizeof(int32_t) * (size_t)n);
+    if (rel_out)
+        for (int64_t s = 0; s < n; ++s)
+            memcpy(&rel_out[4 * s], &rel[4 * (int64_t)g.order[s]], 4 * sizeof(float));
+    free(rel);
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Eq. 3, spline softening.  F(d) = f(r) d with                               */
+/*   f = (10 - 15u + 6u^2) / eps^3   for u = r/eps < 1,                       */
+/*   f = 1 / r^3                     otherwise.                               */
+/* f_over_r_deriv is h = f'(r)/r, used by the Jacobian H = f I + h d d^T:      */
+/*   h = (12u - 15) / (eps^4 r)      for u < 1,                               */
+/*   h = -3 / r^5                    otherwise.                               */
+/* ------------------------------------------------------------------------- */
+static double spline_f(double r, double eps)
+{
+    double u = r / eps;
+    if (u < 1.0) return (10.0 - 15.0 * u + 6.0 * u * u) / (eps * eps * eps);
+    return 1.0 / (r * r * r);
+}
+
+static double spline_h(double r, double eps)
+{
+    double u = r / eps;
+    if (u < 1.0) return (12.0 * u - 15.0) / (eps * eps * eps * eps * r);
+    return -3.0 / (r * r * r * r * r);
+}
+
+/*
+ * The image of source j seen from sink i: for each axis the integer shift m
+ * that brings the unwrapped cell difference into [-R, R]; returns 0 if j is not
+ * in the near field of i (some axis has no such shift).  The displacement is
+ * d = (x_j + m L) - x_i in FP64.
+ */
+static int nf_displacement(const grid_t *g, const float *pos, double L, int64_t R,
+                           int64_t i, int64_t j, double d[3])
+{
+    int64_t K = g->K;
+    for (int a = 0; a < 3; ++a) {
+        int64_t dc = g->cu[3 * j + a] - g->cu[3 * i + a];
+        /* residue of dc in [-R, R] modulo K; unique because K >= 2R+1 */
+        int64_t r = dc % K;
+        if (r < 0) r += K;
+        if (r > R) r -= K;
+        if (r < -R || r > R) return 0;
+        int64_t m = (r - dc) / K; /* exact: r - dc is a multiple of K */
+        d[a] = ((double)pos[3 * j + a] + (double)m * L) - (double)pos[3 * i + a];
+    }
+    return 1;
+}
+
+/* Visit every near-field source j of sink i: the (2R+1)^3 cells around i's cell
+ * (periodic in the cell index), every particle in them except i itself. */
+typedef void (*pair_fn)(void *ctx, int64_t i, int64_t j, const double d[3]);
+
+static int64_t visit_near_field(const grid_t *g, const float *pos, double L, int64_t R,
+                                int64_t i, pair_fn fn, void *ctx)
+{
+    int64_t K = g->K, npairs = 0;
+    int64_t ci[3];
+    for (int a = 0; a < 3; ++a) {
+        ci[a] = g->cu[3 * i + a] % K;
+        if (ci[a] < 0) ci[a] += K;
+    }
+    for (int64_t ox = -R; ox <= R; ++ox)
+        for (int64_t oy = -R; oy <= R; ++oy)
+            for (int64_t oz = -R; oz <= R; ++oz) {
+                int64_t cx = ((ci[0] + ox) % K + K) % K;
+                int64_t cy = ((ci[1] + oy) % K + K) % K;
+                int64_t cz = ((ci[2] + oz) % K + K) % K;
+                int64_t c = (cx * K + cy) * K + cz;
+                for (int32_t s = g->start[c]; s < g->start[c + 1]; ++s) {
+                    int64_t j = g->order[s];
+                    if (j == i) continue;
+                    double d[3];
+                    if (!nf_displacement(g, pos, L, R, i, j, d)) continue; /* never for K >= 2R+1 */
+                    fn(ctx, i, j, d);
+                    ++npairs;
+                }
+            }
+    return npairs;
+}
+
+typedef struct { double eps; double a[3]; } force_ctx;
+
+static void force_pair(void *vctx, int64_t i, int64_t j, const double d[3])
+{
+    (void)i; (void)j;
+    force_ctx *ctx = (force_ctx *)vctx;
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (r == 0.0) return; /* coincident: F(0) = f(0) * 0 = 0 */
+    double f = spline_f(r, ctx->eps);
+    for (int a = 0; a < 3; ++a) ctx->a[a] += f * d[a];
+}
+
+/*
+ * oracle_forces: near-field acceleration (box units, G*m = 1, attractive) of the
+ * sinks listed in sinks[0..nsink) (all particles if sinks == NULL, nsink == n).
+ * acc is nsink x 3 FP64.  *npairs (optional) receives the number of ordered
+ * (sink, source) pairs summed.
+ */
+int oracle_forces(int64_t n, const float *pos, double L, int32_t K, int32_t R, double eps_p,
+                  int64_t nsink, const int64_t *sinks, double *acc, int64_t *npairs)
+{
+    int rc = check_box(L, K, R, eps_p);
+    if (rc) return rc;
+    if (n < 0 || nsink < 0 || (n > 0 && !pos) || (nsink > 0 && !acc)) return ORACLE_EINVAL;
+    grid_t g;
+    rc = grid_build(&g, n, pos, L, K, NULL);
+    if (rc) return rc;
+    int64_t total = 0;
+    force_ctx ctx;
+    ctx.eps = SPLINE_OVER_PLUMMER * eps_p;
+    for (int64_t k = 0; k < nsink; ++k) {
+        int64_t i = sinks ? sinks[k] : k;
+        if (i < 0 || i >= n) { grid_free(&g); return ORACLE_EINVAL; }
+        ctx.a[0] = ctx.a[1] = ctx.a[2] = 0.0;
+        total += visit_near_field(&g, pos, L, R, i, force_pair, &ctx);
+        for (int a = 0; a < 3; ++a) acc[3 * k + a] = ctx.a[a];
+    }
+    if (npairs) *npairs = total;
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+typedef struct { double eps; const float *w; double g[3]; } vjp_ctx;
+
+static void vjp_pair(void *vctx, int64_t k, int64_t j, const double d[3])
+{
+    vjp_ctx *ctx = (vjp_ctx *)vctx;
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = (double)ctx->w[3 * j + a] - (double)ctx->w[3 * k + a];
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (r == 0.0) {
+        /* limit r -> 0: H = f(0) I, the d d^T term vanishes */
+        double f0 = spline_f(0.0, ctx->eps);
+        for (int a = 0; a < 3; ++a) ctx->g[a] += f0 * v[a];
+        return;
+    }
+    double f = spline_f(r, ctx->eps);
+    double h = spline_h(r, ctx->eps);
+    double dv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
+    for (int a = 0; a < 3; ++a) ctx->g[a] += f * v[a] + h * dv * d[a];
+}
+
+/*
+ * oracle_vjp: g_k = dL/dx_k for L = sum_i w_i . a_i with the binning frozen,
+ *   g_k = sum_{j in NF(k)} H(d_kj) (w_j - w_k),   H = f I + h d d^T,
+ * for the particles listed in sinks (all if NULL).  g is nsink x 3 FP64 in box
+ * units (a is box units, so g has units of a / length).
+ */
+int oracle_vjp(int64_t n, const float *pos, const float *w, double L, int32_t K, int32_t R,
+               double eps_p, int64_t nsink, const int64_t *sinks, double *g_out)
+{
+    int rc = check_box(L, K, R, eps_p);
+    if (rc) return rc;
+    if (n < 0 || nsink < 0 || (n > 0 && (!pos || !w)) || (nsink > 0 && !g_out)) return ORACLE_EINVAL;
+    grid_t g;
+    rc = grid_build(&g, n, pos, L, K, NULL);
+    if (rc) return rc;
+    vjp_ctx ctx;
+    ctx.eps = SPLINE_OVER_PLUMMER * eps_p;
+    ctx.w = w;
+    for (int64_t q = 0; q < nsink; ++q) {
+        int64_t k = sinks ? sinks[q] : q;
+        if (k < 0 || k >= n) { grid_free(&g); return ORACLE_EINVAL; }
+        ctx.g[0] = ctx.g[1] = ctx.g[2] = 0.0;
+        visit_near_field(&g, pos, L, R, k, vjp_pair, &ctx);
+        for (int a = 0; a < 3; ++a) g_out[3 * q + a] = ctx.g[a];
+    }
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+typedef struct { double eps; const float *w; int axis; double h; double sum; } fd_ctx;
+
+static void fd_pair(void *vctx, int64_t k, int64_t j, const double d[3])
+{
+    fd_ctx *ctx = (fd_ctx *)vctx;
+    double dm[3] = {d[0], d[1], d[2]}, dp[3] = {d[0], d[1], d[2]};
+    dm[ctx->axis] -= ctx->h;
+    dp[ctx->axis] += ctx->h;
+    double rm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
+    double rp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
+    double fm = rm == 0.0 ? 0.0 : spline_f(rm, ctx->eps);
+    double fp = rp == 0.0 ? 0.0 : spline_f(rp, ctx->eps);
+    for (int a = 0; a < 3; ++a) {
+        double wk_minus_wj = (double)ctx->w[3 * k + a] - (double)ctx->w[3 * j + a];
+        ctx->sum += wk_minus_wj * (fm * dm[a] - fp * dp[a]);
+    }
+}
+
+/*
+ * oracle_fd: central difference of L = sum_i w_i . a_i with respect to x_{k,axis}
+ * at step h, binning and images frozen:
+ *   D(h) = sum_{j in NF(k)} (w_k - w_j) . [F(d_kj - h e) - F(d_kj + h e)] / (2h),
+ * which is exactly (L(x + h e_k) - L(x - h e_k)) / (2h) because F is odd and the
+ * near-field relation is symmetric.
+ */
+int oracle_fd(int64_t n, const float *pos, const float *w, double L, int32_t K, int32_t R,
+              double eps_p, int64_t k, int32_t axis, double h, double *out)
+{
+    int rc = check_box(L, K, R, eps_p);
+    if (rc) return rc;
+    if (n <= 0 || !pos || !w || !out || k < 0 || k >= n || axis < 0 || axis > 2 || !(h > 0.0))
+        return ORACLE_EINVAL;
+    grid_t g;
+    rc = grid_build(&g, n, pos, L, K, NULL);
+    if (rc) return rc;
+    fd_ctx ctx;
+    ctx.eps = SPLINE_OVER_PLUMMER * eps_p;
+    ctx.w = w; ctx.axis = axis; ctx.h = h; ctx.sum = 0.0;
+    visit_near_field(&g, pos, L, R, k, fd_pair, &ctx);
+    *out = ctx.sum / (2.0 * h);
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+/* The softening conversion constant, exported so tests can check it. */
+double oracle_spline_over_plummer(void) { return SPLINE_OVER_PLUMMER; }
+
+/* Eq. 3 for one separation, exported for the closed-form tests. */
+double oracle_pair_f(double r, double eps_s) { return spline_f(r, eps_s); }
+double oracle_pair_h(double r, double eps_s) { return spline_h(r, eps_s); }

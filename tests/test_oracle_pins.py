@@ -1,0 +1,406 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each one checks it against
+an independent route -- a numpy/torch implementation written differently, a
+closed form (Newton's law, the Plummer limit of Eq. 2, the linear system that
+defines Eq. 3), a number the paper prints (tests/golden), or an invariant of the
+exact near-field sum (antisymmetry, centred lattice, translation, scaling, pair
+coverage).
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_2110_11392_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Binning: textbook numpy routines, exact rational arithmetic, faces and wrap
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,cpd,box,seed", [(3000, 8, 1.0, 1), (5000, 7, 1.0, 2),
+                                             (4000, 11, 3.7, 3), (1, 5, 1.0, 4)])
+def test_bin_matches_numpy_counting_sort(n, cpd, box, seed):
+    pos = synth.uniform(n, seed, box)
+    cell, offs, perm, rel = oracle.bin(pos, box, cpd)
+    t = pos.astype(np.float64) * (float(cpd) / box)
+    fl = np.floor(t)
+    c = np.mod(fl.astype(np.int64), cpd)
+    ref_cell = (c[:, 0] * cpd + c[:, 1]) * cpd + c[:, 2]
+    assert np.array_equal(cell, ref_cell)
+    counts = np.bincount(ref_cell, minlength=cpd ** 3)
+    assert np.array_equal(offs, np.concatenate([[0], np.cumsum(counts)]))
+    ref_perm = np.argsort(ref_cell, kind="stable")
+    assert np.array_equal(perm, ref_perm)
+    ref_rel = (t - (fl + 0.5)).astype(np.float32)[ref_perm]
+    assert np.array_equal(rel[:, :3].view(np.uint32), ref_rel.view(np.uint32))
+    assert np.all(rel[:, 3] == 0)
+
+
+def test_bin_offsets_are_one_rounding_of_the_exact_value():
+    """Each cell-relative offset is the exact rational t - (floor(t) + 1/2) rounded
+    once to FP32; for L = 1, K = 2^k and x >= 1/2 no rounding happens at all."""
+    pos = synth.clustered(2000, 8, 32, 77)
+    _, _, perm, rel = oracle.bin(pos, 1.0, 32)
+    for s in range(0, 2000, 7):
+        for a in range(3):
+            xf = float(pos[perm[s], a])
+            t = Fraction(xf) * 32
+            exact = t - (math.floor(t) + Fraction(1, 2))
+            assert float(exact) == exact                     # representable in FP64
+            assert rel[s, a] == np.float32(float(exact))     # one rounding to FP32
+            if xf >= 0.5:
+                assert Fraction(float(rel[s, a])) == exact
+
+
+def test_bin_faces_and_wrap():
+    K = 8
+    w = np.float32(1.0 / K)
+    pos = np.array([
+        [0.0, 0.0, 0.0],                 # lower corner of cell 0
+        [w, 2 * w, 3 * w],               # exactly on faces -> the higher cell
+        [1.0, 1.0, 1.0],                 # x = L -> cell 0, offset -1/2
+        [-w / 2, 0.5, 0.25],             # negative -> periodic image
+        [1.0 + w / 4, 0.5, 0.5],         # beyond L -> periodic image
+        [np.nextafter(np.float32(1.0), np.float32(0.0)), 0.0, 0.0],
+    ], dtype=np.float32)
+    cell, offs, perm, rel = oracle.bin(pos, 1.0, K)
+    cx = cell // (K * K)
+    cy = (cell // K) % K
+    cz = cell % K
+    assert (cx[0], cy[0], cz[0]) == (0, 0, 0)
+    assert (cx[1], cy[1], cz[1]) == (1, 2, 3)
+    assert (cx[2], cy[2], cz[2]) == (0, 0, 0)
+    assert (cx[3], cy[3], cz[3]) == (7, 4, 2)
+    assert cx[4] == 0
+    assert cx[5] == 7
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    assert np.all(rel[inv[0], :3] == -0.5)
+    assert np.all(rel[inv[2], :3] == -0.5)
+    assert rel[inv[1], 0] == -0.5 and rel[inv[1], 1] == -0.5
+    assert rel[inv[3], 0] == 0.0          # -w/2 sits at the centre of cell -1 == 7
+    assert rel[inv[4], 0] == np.float32(-0.25)
+
+
+def test_bin_rejects_non_finite():
+    pos = np.zeros((4, 3), np.float32)
+    pos[2, 1] = np.inf
+    with pytest.raises(oracle.OracleError):
+        oracle.bin(pos, 1.0, 8)
+    pos[2, 1] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.bin(pos, 1.0, 8)
+
+
+# --------------------------------------------------------------------------
+# Eq. 3 from the paper's construction, Newton, Plummer
+# --------------------------------------------------------------------------
+
+def test_softening_constant_matches_paper():
+    g = golden()
+    assert oracle.spline_over_plummer() == g["spline_over_plummer"]["value"]
+
+
+def _spline_coefficients_from_matching():
+    """Solve for F(r) = (a + b u + c u^2) r / eps^3 matched in value, slope and
+    curvature to |F| = 1/r^2 at u = r/eps = 1 (Sec. 3.2: smooth up to the second
+    derivative).  In units eps = 1, |F|(u) = a u + b u^2 + c u^3."""
+    # rows: value, first, second derivative of a u + b u^2 + c u^3 at u = 1
+    m = np.array([[1.0, 1.0, 1.0],
+                  [1.0, 2.0, 3.0],
+                  [0.0, 2.0, 6.0]])
+    # the same derivatives of u^-2 at u = 1: 1, -2, 6
+    rhs = np.array([1.0, -2.0, 6.0])
+    return np.linalg.solve(m, rhs)
+
+
+def test_eq3_is_the_c2_matched_spline():
+    assert golden()["spline_matching_order"]["value"] == 2
+    a, b, c = _spline_coefficients_from_matching()
+    eps = 0.0135
+    for u in np.linspace(0.0, 0.999, 41):
+        r = u * eps
+        expect = (a + b * u + c * u * u) / eps ** 3
+        assert oracle.pair_f(r, eps) == pytest.approx(expect, rel=1e-12, abs=0)
+
+
+@pytest.mark.parametrize("u", [1.0, 1.001, 1.5, 3.0, 17.0, 250.0])
+def test_eq3_is_newton_outside_eps(u):
+    eps = 0.0135
+    r = u * eps
+    assert oracle.pair_f(r, eps) == pytest.approx(r ** -3, rel=1e-14)
+
+
+def test_eq3_continuity_at_eps():
+    """Force, slope and curvature of |F| = f(r) r are continuous at r = eps."""
+    eps = 0.25
+    g = lambda r: oracle.pair_f(r, eps) * r
+    h = 1e-4 * eps
+    left = [g(eps - k * h) for k in (1, 2, 3)]
+    right = [g(eps + k * h) for k in (1, 2, 3)]
+    # one-sided derivatives from each side agree with 1/r^2's at eps
+    d1l = (3 * g(eps) - 4 * left[0] + left[1]) / (2 * h)
+    d1r = (-3 * g(eps) + 4 * right[0] - right[1]) / (2 * h)
+    assert g(eps) == pytest.approx(eps ** -2, rel=1e-12)
+    assert d1l == pytest.approx(-2 * eps ** -3, rel=1e-6)
+    assert d1r == pytest.approx(-2 * eps ** -3, rel=1e-6)
+    d2l = (2 * g(eps) - 5 * left[0] + 4 * left[1] - left[2]) / h ** 2
+    d2r = (2 * g(eps) - 5 * right[0] + 4 * right[1] - right[2]) / h ** 2
+    assert d2l == pytest.approx(6 * eps ** -4, rel=1e-3)
+    assert d2r == pytest.approx(6 * eps ** -4, rel=1e-3)
+
+
+def test_plummer_small_r_limit():
+    """At small r the spline with eps_s = 2.16 eps_p reproduces Plummer's
+    r/(r^2+eps_p^2)^(3/2) (Eq. 2) -> r/eps_p^3 to the precision of the printed
+    constant 2.16 (the exact match would be 10^(1/3) = 2.1544)."""
+    eps_p = 1e-3
+    eps_s = oracle.spline_over_plummer() * eps_p
+    r = 1e-9
+    plummer = 1.0 / (r * r + eps_p * eps_p) ** 1.5
+    ratio = oracle.pair_f(r, eps_s) / plummer
+    assert abs(ratio - 1.0) < 0.008
+    assert ratio == pytest.approx(10.0 ** 1 / 2.16 ** 3, rel=1e-6)
+
+
+@pytest.mark.parametrize("u", [0.05, 0.3, 0.7, 0.999, 1.001, 1.3, 4.0])
+def test_h_is_derivative_of_f(u):
+    eps = 0.02
+    r = u * eps
+    dr = 1e-6 * r
+    deriv = (oracle.pair_f(r + dr, eps) - oracle.pair_f(r - dr, eps)) / (2 * dr)
+    assert oracle.pair_h(r, eps) == pytest.approx(deriv / r, rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Two bodies: closed forms, stencil boundary, periodic wrap
+# --------------------------------------------------------------------------
+
+def _newton_or_spline(d, eps):
+    a, b, c = _spline_coefficients_from_matching()
+    r = float(np.linalg.norm(d))
+    u = r / eps
+    if u >= 1.0:
+        return d / r ** 3
+    return (a + b * u + c * u * u) / eps ** 3 * d
+
+
+@pytest.mark.parametrize("u", [0.3, 0.999, 1.0, 1.001, 3.0])
+@pytest.mark.parametrize("where", ["same_cell", "across_face", "across_wrap"])
+def test_two_body(u, where):
+    K, R, eps_p = 8, 2, 1.0 / 640
+    eps = 2.16 * eps_p
+    w = 1.0 / K
+    direction = np.array([0.6, -0.48, 0.64])
+    base = {"same_cell": [0.3 * w, 2.4 * w, 5.5 * w],
+            "across_face": [3 * w - 0.2 * u * eps, 4.5 * w, 4.5 * w],
+            "across_wrap": [1.0 - 0.3 * u * eps, 0.5, 0.5]}[where]
+    x1 = np.array(base, dtype=np.float32)
+    x2 = (x1.astype(np.float64) + u * eps * direction)
+    x2 = np.mod(x2, 1.0).astype(np.float32)
+    pos = np.stack([x1, x2])
+    acc, npairs = oracle.forces(pos, 1.0, K, R, eps_p)
+    d = pos[1].astype(np.float64) - pos[0].astype(np.float64)
+    d -= np.rint(d)
+    expect = _newton_or_spline(d, eps)
+    assert npairs == 2
+    assert acc[0] == pytest.approx(expect, rel=1e-12, abs=1e-300)
+    assert np.array_equal(acc[1], -acc[0])
+
+
+@pytest.mark.parametrize("offset,inside", [(2, True), (3, False), (-2, True), (-3, False),
+                                           (5, False), (6, True)])
+def test_stencil_boundary_by_cell_offset(offset, inside):
+    """A source R cells away interacts; R+1 cells away does not (periodic, K=8)."""
+    K, R = 8, 2
+    w = 1.0 / K
+    x1 = np.array([1.5 * w, 4.5 * w, 4.5 * w], np.float32)
+    x2 = np.array([((1 + offset) % K + 0.5) * w, 4.5 * w, 4.5 * w], np.float32)
+    acc, npairs = oracle.forces(np.stack([x1, x2]), 1.0, K, R, 1.0 / 640)
+    if inside:
+        assert npairs == 2
+        dx = ((offset + K // 2) % K - K // 2) * w
+        assert acc[0, 0] == pytest.approx(np.sign(dx) / dx ** 2, rel=1e-12)
+    else:
+        assert npairs == 0
+        assert np.all(acc == 0)
+
+
+def test_neighbour_cell_count_matches_paper():
+    """One particle per cell: each sees exactly (2R+1)^3 - 1 = 124 others for R=2
+    (Sec. 3.4.1), and every force vanishes by symmetry."""
+    g = golden()
+    K, R = 8, g["neighbour_cells_R2"]["radius"]
+    w = 1.0 / K
+    idx = np.stack(np.meshgrid(np.arange(K), np.arange(K), np.arange(K), indexing="ij"), -1)
+    pos = ((idx.reshape(-1, 3) + 0.5) * w).astype(np.float32)
+    acc, npairs = oracle.forces(pos, 1.0, K, R, 1.0 / 640)
+    assert npairs == K ** 3 * g["neighbour_cells_R2"]["value"]
+    assert (2 * R + 1) == g["stencil_width_R2"]["value"]
+    assert np.max(np.abs(acc)) < 1e-10 * (1.0 / w ** 2)
+
+
+def test_centred_symmetric_pattern_gives_zero():
+    """Each cell holds a particle at its centre plus a pair placed symmetrically
+    about it: the near field of every centre particle cancels exactly."""
+    K, R = 7, 2
+    w = 1.0 / 8.0   # use L = 7/8 so that w is a power of two
+    box = K * w
+    rng = np.random.default_rng(5)
+    rows = []
+    off = (rng.integers(-100, 100, size=3) / 1024.0) * w
+    for cx in range(K):
+        for cy in range(K):
+            for cz in range(K):
+                c = (np.array([cx, cy, cz]) + 0.5) * w
+                rows += [c, c + off, c - off]
+    pos = np.array(rows, dtype=np.float32)
+    centres = np.arange(0, pos.shape[0], 3)
+    acc, _ = oracle.forces(pos, box, K, R, 1.0 / 640, sinks=centres)
+    scale = 1.0 / w ** 2
+    assert np.max(np.abs(acc)) < 1e-12 * scale
+
+
+# --------------------------------------------------------------------------
+# Whole near-field sum: brute force, invariants, pair coverage
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,n,cpd,seed", [("uniform", 1500, 7, 11), ("clustered", 2000, 8, 12),
+                                             ("clustered", 1200, 9, 13), ("uniform", 900, 7, 14)])
+def test_oracle_matches_brute_force(kind, n, cpd, seed):
+    pos = synth.uniform(n, seed) if kind == "uniform" else synth.clustered(n, 6, cpd, seed)
+    eps_p = 1.0 / (40 * n ** (1 / 3))
+    acc, npairs = oracle.forces(pos, 1.0, cpd, 2, eps_p)
+    ref, ref_pairs = brute.forces(pos, 1.0, cpd, 2, eps_p)
+    assert npairs == ref_pairs
+    err = np.linalg.norm(acc - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+    assert np.max(err) < 1e-10
+
+
+def test_full_c1_matches_brute_force():
+    b = synth.config("C1")[0]
+    acc, npairs = oracle.forces(b.pos, b.box, b.cpd, b.radius, b.eps_plummer)
+    ref, ref_pairs = brute.forces(b.pos, b.box, b.cpd, b.radius, b.eps_plummer, chunk=128)
+    assert npairs == ref_pairs
+    err = np.linalg.norm(acc - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.max(err) < 1e-10
+
+
+def _pair_count_from_counts(pos, box, cpd, radius):
+    c = brute.cells(pos, box, cpd)
+    cell = (c[:, 0] * cpd + c[:, 1]) * cpd + c[:, 2]
+    n = np.bincount(cell, minlength=cpd ** 3).reshape(cpd, cpd, cpd).astype(np.int64)
+    s = np.zeros_like(n)
+    for ox in range(-radius, radius + 1):
+        for oy in range(-radius, radius + 1):
+            for oz in range(-radius, radius + 1):
+                s += np.roll(n, (ox, oy, oz), axis=(0, 1, 2))
+    return int((n * s).sum()) - pos.shape[0]
+
+
+def test_pair_coverage_exact():
+    pos = synth.clustered(6000, 10, 9, 21)
+    _, npairs = oracle.forces(pos, 1.0, 9, 2, 1e-3)
+    assert npairs == _pair_count_from_counts(pos, 1.0, 9, 2)
+
+
+def test_antisymmetry_total_force_vanishes():
+    pos = synth.clustered(8000, 12, 10, 31)
+    acc, _ = oracle.forces(pos, 1.0, 10, 2, 1.0 / 800)
+    total = np.abs(acc.sum(axis=0))
+    assert np.all(total <= 1e-13 * np.abs(acc).sum(axis=0))
+
+
+def test_translation_by_whole_cells():
+    K, R = 8, 2
+    rng = np.random.default_rng(41)
+    pos = (rng.integers(0, 2 ** 20, size=(1500, 3)) / 2 ** 20).astype(np.float32)
+    shift = np.array([3, -2, 5]) / K
+    moved = np.mod(pos.astype(np.float64) + shift, 1.0).astype(np.float32)
+    assert np.array_equal(np.mod(moved.astype(np.float64) - shift, 1.0).astype(np.float32), pos)
+    a0, p0 = oracle.forces(pos, 1.0, K, R, 1.0 / 500)
+    a1, p1 = oracle.forces(moved, 1.0, K, R, 1.0 / 500)
+    assert p0 == p1
+    assert np.allclose(a0, a1, rtol=1e-13, atol=0)
+
+
+def test_scaling_by_power_of_two():
+    K, R = 8, 2
+    pos = synth.clustered(1500, 5, K, 51)
+    a1, _ = oracle.forces(pos, 1.0, K, R, 1.0 / 500)
+    a2, _ = oracle.forces(pos * np.float32(4.0), 4.0, K, R, 4.0 / 500)
+    assert np.array_equal(a2, a1 / 16.0)
+
+
+# --------------------------------------------------------------------------
+# Gradient: finite differences, torch autograd of a brute-force sum, identities
+# --------------------------------------------------------------------------
+
+def test_vjp_matches_richardson_fd():
+    n, K, R = 2000, 8, 2
+    pos = synth.clustered(n, 8, K, 61)
+    w = synth.gaussian_weights(n, 62)
+    eps_p = 1.0 / 500
+    rng = np.random.default_rng(63)
+    ks = rng.choice(n, size=24, replace=False)
+    axes = rng.integers(0, 3, size=24)
+    g = oracle.vjp(pos, w, 1.0, K, R, eps_p, sinks=ks)
+    for q, (k, a) in enumerate(zip(ks, axes)):
+        fd = oracle.fd_richardson(pos, w, 1.0, K, R, eps_p, int(k), int(a), 1e-3 * 2.16 * eps_p)
+        assert fd == pytest.approx(g[q, a], rel=1e-6, abs=1e-9 * np.abs(g[q]).max())
+
+
+def test_vjp_matches_torch_autograd_of_brute_force():
+    torch = pytest.importorskip("torch")
+    n, K, R = 400, 7, 2
+    pos = synth.clustered(n, 4, K, 71)
+    w = synth.gaussian_weights(n, 72)
+    eps_p = 1.0 / 300
+    eps = 2.16 * eps_p
+    c = torch.from_numpy(brute.cells(pos, 1.0, K))
+    dc = torch.remainder(c[None, :, :] - c[:, None, :] + R, K) - R
+    near = (dc.abs() <= R).all(dim=2) & ~torch.eye(n, dtype=torch.bool)
+    x = torch.tensor(pos, dtype=torch.float64, requires_grad=True)
+    d = x[None, :, :] - x[:, None, :]
+    d = d - torch.round(d.detach())                     # minimum image, frozen
+    r = torch.sqrt((d * d).sum(-1) + (~near).double())  # avoid r=0 off the near field
+    u = r / eps
+    ca, cb, cc = _spline_coefficients_from_matching()
+    f = torch.where(u < 1, (ca + cb * u + cc * u * u) / eps ** 3, r ** -3)
+    f = torch.where(near, f, torch.zeros_like(f))
+    a = (f[:, :, None] * d).sum(1)
+    loss = (a * torch.from_numpy(w.astype(np.float64))).sum()
+    loss.backward()
+    g = oracle.vjp(pos, w, 1.0, K, R, eps_p)
+    ref = x.grad.numpy()
+    assert np.linalg.norm(g - ref) <= 1e-11 * np.linalg.norm(ref)
+    acc, _ = oracle.forces(pos, 1.0, K, R, eps_p)
+    assert np.allclose(acc, a.detach().numpy(), rtol=1e-11, atol=0)
+
+
+def test_vjp_sums_to_zero_and_is_symmetric():
+    n, K, R = 3000, 8, 2
+    pos = synth.clustered(n, 8, K, 81)
+    w = synth.gaussian_weights(n, 82)
+    v = synth.gaussian_weights(n, 83)
+    eps_p = 1.0 / 600
+    gw = oracle.vjp(pos, w, 1.0, K, R, eps_p)
+    gv = oracle.vjp(pos, v, 1.0, K, R, eps_p)
+    assert np.all(np.abs(gw.sum(0)) <= 1e-12 * np.abs(gw).sum(0))
+    lhs = float(np.sum(v.astype(np.float64) * gw))
+    rhs = float(np.sum(w.astype(np.float64) * gv))
+    assert lhs == pytest.approx(rhs, rel=1e-11)

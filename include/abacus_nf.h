@@ -1,0 +1,171 @@
+/*
+ * abacus_nf.h -- C ABI of the MI355X near-field force library.
+ *
+ * The near field of the Abacus method (Garrison et al. 2021): particles are
+ * binned into a periodic K^3 grid of cells (Sec. 2.2) and every particle
+ * receives the exact, direct, softened 1/r^2 force of every other particle in
+ * the (2R+1)^3 cells around its own cell (Sec. 3.4.1), using the periodic image
+ * that lies in the neighbouring cell (Sec. 3.4.2).  The force law is the
+ * spline softening of Eq. 3 with eps_s = 2.16 eps_p (Sec. 3.2).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers on the current HIP device,
+ *     allocated and owned by the caller.  Nothing is allocated, freed or
+ *     synchronised by the library; every call only enqueues work on `stream`
+ *     (a hipStream_t passed as void*, NULL = the null stream) and returns.  The
+ *     enqueued work can be captured into a HIP graph.
+ *   - `boxes` / `nboxes` is a HOST array.  Several independent periodic boxes
+ *     can be processed by one call: their particles are concatenated in box
+ *     order (box b owns particles [first_b, first_b + n_b), first_b = sum of the
+ *     n of earlier boxes) and so are their cells (box b owns global cell ids
+ *     [cell_base_b, cell_base_b + K_b^3), cell_base_b = sum of earlier K^3).
+ *   - Units: G*m = 1 for every particle (equal unit masses).  Accelerations
+ *     are attractive, in box-length units: a_i = sum_j F(x_j - x_i).
+ *   - Return value: ABACUS_NF_OK (0) or a negative error code.  Argument
+ *     errors are detected on the host before anything is enqueued (outputs are
+ *     untouched).  Problems only visible in the data (non-finite positions) set
+ *     bits in the device status word of the binned arrays; outputs for such a
+ *     call are unspecified.
+ *   - A workspace (`ws`, `ws_bytes`, device memory, 256-byte aligned) holds
+ *     all temporaries; size it with abacus_nf_workspace_bytes.  Calls that
+ *     share a workspace must be ordered on one stream.
+ */
+#ifndef ABACUS_NF_H
+#define ABACUS_NF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define ABACUS_NF_OK          0
+#define ABACUS_NF_EINVAL     (-1)  /* bad argument (null pointer, box, K, R, softening, flags) */
+#define ABACUS_NF_ERANGE     (-2)  /* sizes beyond the int32 index space of the kernels */
+#define ABACUS_NF_EWORKSPACE (-3)  /* workspace missing, misaligned or too small */
+#define ABACUS_NF_EHIP       (-4)  /* a HIP runtime call failed; see abacus_nf_strerror */
+
+/* ---- device status bits (int32 written by abacus_nf_bin) ---------------- */
+#define ABACUS_NF_STATUS_BADPOS 0x1  /* a coordinate was non-finite or |x K / L| >= 2^30 */
+
+/* ---- flags for abacus_nf_forces / abacus_nf_forces_vjp ----------------- */
+/* Accumulation of each sink's sum (exactly one of the three; default COMPENSATED):
+ *   SINGLE_ACC   one FP32 accumulator per sink, every pair added in turn (the
+ *                register accumulation of the paper's kernel, Sec. 3.4.2);
+ *   CHUNKED      FP32 partial sums over chunks of at most 64 sources of one
+ *                cell, added to the accumulator (the "intermediate
+ *                accumulators" remedy named in Sec. 3.5.4);
+ *   COMPENSATED  the same chunk partials folded into an FP32 (sum, error) pair
+ *                with an error-free TwoSum (the Kahan-style remedy of
+ *                Sec. 3.5.4). */
+#define ABACUS_NF_SINGLE_ACC   0x1u
+#define ABACUS_NF_CHUNKED      0x2u
+#define ABACUS_NF_COMPENSATED  0x4u
+/* Debug: count every evaluated (sink, source) pair, self excluded, into the
+ * int64 at `pair_count` (abacus_nf_forces only).  Costs one atomic per work item. */
+#define ABACUS_NF_COUNT_PAIRS  0x10u
+
+/* ---- data types --------------------------------------------------------- */
+
+/* One periodic box (Sec. 2.2 grid; Sec. 3.4.1 near-field radius; Sec. 3.2
+ * softening).  Requirements: n >= 0; box > 0 and finite; radius >= 0;
+ * cpd >= 2*radius + 1 (so the (2R+1)^3 stencil never wraps onto itself);
+ * eps_plummer > 0 and finite with 1e-6 <= 2.16*eps_plummer*cpd/box <= 1e6. */
+typedef struct {
+    int64_t n;             /* number of particles in this box */
+    double  box;           /* side L of the periodic cube */
+    int32_t cpd;           /* cells per dimension K */
+    int32_t radius;        /* near-field radius R in cells (the paper uses 2) */
+    double  eps_plummer;   /* Plummer-equivalent softening; eps_s = 2.16 eps_p */
+} abacus_nf_box;
+
+/* Binned particles: the output of abacus_nf_bin, input of the force calls.
+ * Sorted order is by global cell id (box, then x slowest, z fastest), and by
+ * ascending original index inside a cell (a stable counting sort). */
+typedef struct {
+    int32_t *cell_offsets; /* cells_total + 1: first sorted slot of each global cell;
+                              cell_offsets[cells_total] = n_total */
+    int32_t *perm;         /* n_total: sorted slot -> original (global) particle index */
+    float   *rel;          /* n_total x 4: in sorted order, (x, y, z) offset from the
+                              cell centre in cell-width units, in [-1/2, 1/2); 4th = 0 */
+    int32_t *status;       /* 1 int: ABACUS_NF_STATUS_* bits, written by abacus_nf_bin */
+} abacus_nf_binned;
+
+/* ---- entry points ------------------------------------------------------- */
+
+/* Totals of a box list: *n_total = sum n, *cells_total = sum K^3.
+ * EINVAL on a bad box, ERANGE if either total reaches 2^31. */
+int abacus_nf_layout(const abacus_nf_box *boxes, int nboxes, int64_t *n_total,
+                     int64_t *cells_total);
+
+/* Bytes of workspace that abacus_nf_bin, abacus_nf_forces and
+ * abacus_nf_forces_vjp need for this box list (one workspace serves all three). */
+int abacus_nf_workspace_bytes(const abacus_nf_box *boxes, int nboxes, size_t *bytes);
+
+/*
+ * abacus_nf_bin -- cell assignment and stable counting sort by cell.
+ * Follows Sec. 2.2 (grid of K^3 cells, slabs along x, pencils along z) and
+ * Sec. 3.5.1 (positions kept as FP32 offsets from cell centres).
+ *   pos  n_total x 3 FP32, global coordinates, row-major.  Any finite value is
+ *        taken as its periodic image: with t = x * (K/L) in FP64, the cell is
+ *        floor(t) mod K and the offset is t - (floor(t) + 1/2) rounded once to
+ *        FP32 (a coordinate on a face belongs to the higher cell).
+ *   out  caller-allocated arrays (sizes in abacus_nf_binned); all are written.
+ * The status word is cleared and then set if any coordinate is non-finite or
+ * |t| >= 2^30.
+ */
+int abacus_nf_bin(const abacus_nf_box *boxes, int nboxes, const float *pos,
+                  const abacus_nf_binned *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * abacus_nf_forces -- near-field accelerations.
+ * a_i = sum over j != i in the (2R+1)^3 cells around i's cell of F(x_j - x_i)
+ * with F of Eq. 3 (spline softening, eps_s = 2.16 eps_p, Sec. 3.2), the image of
+ * x_j being the one in the neighbouring cell (Sec. 3.4.1-3.4.2).  Arithmetic is
+ * FP32 on cell-relative coordinates; the accumulation follows `flags`.
+ *   b          binned arrays from abacus_nf_bin for the same boxes.
+ *   acc        n_total x 3 FP32 output in ORIGINAL particle order, box units.
+ *   momentum   NULL, or 4*nboxes FP64 outputs: per box (sum a_x, sum a_y,
+ *              sum a_z, sum |a|), reduced in FP64 in a fixed order.  Pair
+ *              antisymmetry makes the first three vanish up to rounding.
+ *   pair_count NULL, or one int64 that receives the number of evaluated pairs
+ *              when ABACUS_NF_COUNT_PAIRS is set.
+ */
+int abacus_nf_forces(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                     float *acc, double *momentum, int64_t *pair_count, uint32_t flags,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * abacus_nf_forces_vjp -- vector-Jacobian product of the accelerations.
+ * For a cotangent w (n_total x 3 FP32, original order) returns
+ *   grad_k = d/dx_k sum_i w_i . a_i
+ *          = sum_{j in NF(k)} [ f(r) (w_j - w_k) + h(r) (d . (w_j - w_k)) d ],
+ * d = x_j - x_k, f(r) d = F(d) of Eq. 3 and h = f'(r)/r, with the binning held
+ * fixed (the near field is piecewise smooth; this is the derivative inside a
+ * piece).  grad is n_total x 3 FP32 in original order (units of a per length).
+ * Same traversal and accumulation flags as abacus_nf_forces.
+ */
+int abacus_nf_forces_vjp(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                         const float *w, float *grad, uint32_t flags, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* Human-readable text for an error code; for ABACUS_NF_EHIP it includes the
+ * message of the last failing HIP call on this thread. */
+const char *abacus_nf_strerror(int code);
+
+/* ---- measurement hooks (not needed for computing) ------------------------ */
+/* When enabled, the library records HIP events around its pair kernels on the
+ * caller's stream; abacus_nf_timing_read returns the summed milliseconds and
+ * launch count per kernel (0 = forward pair kernel, 1 = adjoint pair kernel,
+ * 2 = binning, 3 = work plan) since the last reset, synchronising on the events.
+ * Do not enable while capturing a graph. */
+int abacus_nf_timing_enable(int enable);
+int abacus_nf_timing_read(int kernel, double *ms, int64_t *launches);
+int abacus_nf_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABACUS_NF_H */

@@ -1,0 +1,385 @@
+// C ABI of libabacus_nf: argument validation, parameter resolution, workspace
+// layout, launch sequencing and the measurement hooks.  No device memory is
+// allocated here; every call enqueues work on the caller's stream.
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nf_internal.h"
+
+using namespace anf;
+
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+constexpr int64_t kMaxIndex = (int64_t(1) << 31) - 1;
+constexpr int kMaxBoxes = 65535;
+// Sec. 3.2: the spline softening length is 2.16 times the Plummer-equivalent one.
+constexpr double kSplineOverPlummer = 2.16;
+
+int hip_fail(hipError_t e, const char* what) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+  g_last_hip_error = buf;
+  return ABACUS_NF_EHIP;
+}
+
+#define ANF_HIP(call, what)                           \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, what);  \
+  } while (0)
+
+struct Resolved {
+  std::vector<DevBox> boxes;
+  int64_t n_total = 0, cells_total = 0, pencils_total = 0, max_box_n = 0;
+};
+
+// Step a1: validate every box and derive the kernel constants.
+int resolve(const abacus_nf_box* in, int nboxes, Resolved* out) {
+  if (!in || nboxes < 1 || nboxes > kMaxBoxes) return ABACUS_NF_EINVAL;
+  out->boxes.resize(nboxes);
+  int64_t n_total = 0, cells_total = 0, pencils_total = 0, max_n = 0;
+  for (int b = 0; b < nboxes; ++b) {
+    const abacus_nf_box& x = in[b];
+    if (x.n < 0) return ABACUS_NF_EINVAL;
+    if (!(x.box > 0.0) || !std::isfinite(x.box)) return ABACUS_NF_EINVAL;
+    if (x.radius < 0 || x.cpd < 2 * (int64_t)x.radius + 1) return ABACUS_NF_EINVAL;
+    if (!(x.eps_plummer > 0.0) || !std::isfinite(x.eps_plummer)) return ABACUS_NF_EINVAL;
+    const int64_t K = x.cpd;
+    if (K > 2000) return ABACUS_NF_ERANGE;
+    const int64_t cells = K * K * K;
+    const double cpl = (double)K / x.box;
+    const double eps_s = kSplineOverPlummer * x.eps_plummer;
+    const double e = eps_s * cpl;  // softening in cell widths
+    if (!(e >= 1e-6) || !(e <= 1e6)) return ABACUS_NF_EINVAL;
+    const double iw2 = cpl * cpl, iw3 = cpl * cpl * cpl;
+    if (!std::isfinite(cpl) || !(iw3 < (double)FLT_MAX) || !(iw2 > (double)FLT_MIN))
+      return ABACUS_NF_EINVAL;
+    DevBox& d = out->boxes[b];
+    std::memset(&d, 0, sizeof(d));
+    d.first = n_total;
+    d.n = x.n;
+    d.cell_base = (int32_t)cells_total;
+    d.K = (int32_t)K;
+    d.R = x.radius;
+    d.pencil_base = (int32_t)pencils_total;
+    d.cells_per_len = cpl;
+    d.inv_w2 = (float)iw2;
+    d.inv_w3 = (float)iw3;
+    d.c0 = (float)(10.0 / (e * e * e));
+    d.c1 = (float)(-15.0 / (e * e * e * e));
+    d.c2 = (float)(6.0 / (e * e * e * e * e));
+    d.eps = (float)e;
+    d.ha = (float)(12.0 / (e * e * e * e * e));
+    d.hb = (float)(-15.0 / (e * e * e * e));
+    n_total += x.n;
+    cells_total += cells;
+    pencils_total += K * K;
+    if (x.n > max_n) max_n = x.n;
+    if (n_total > kMaxIndex || cells_total >= kMaxIndex) return ABACUS_NF_ERANGE;
+  }
+  out->n_total = n_total;
+  out->cells_total = cells_total;
+  out->pencils_total = pencils_total;
+  out->max_box_n = max_n;
+  return ABACUS_NF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  // shared
+  size_t boxtab;
+  // binning region
+  size_t counts, keys0, keys1, vals0, vals1, hist, hist_scan, bin_scan;
+  // force / adjoint region (overlaps the binning region)
+  size_t pencil_counts, item_base, items, item_bucket, queue, ctrl, plan_scan, mom, src_w;
+  size_t total;
+  int64_t max_items;
+};
+
+Layout layout(const Resolved& r) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + (bytes ? bytes : 1));
+    return at;
+  };
+  L.boxtab = take(sizeof(DevBox) * r.boxes.size());
+  const size_t region = o;
+  const int64_t n = r.n_total, c = r.cells_total;
+  const int64_t rb = radix_blocks(n);
+  L.counts = take(4 * (size_t)c);
+  L.keys0 = take(4 * (size_t)n);
+  L.keys1 = take(4 * (size_t)n);
+  L.vals0 = take(4 * (size_t)n);
+  L.vals1 = take(4 * (size_t)n);
+  L.hist = take(4 * (size_t)(256 * rb));
+  L.hist_scan = take(4 * (size_t)(256 * rb + 1));
+  int64_t scan_n = c > 256 * rb ? c : 256 * rb;
+  L.bin_scan = take(4 * (size_t)scan_tmp_ints(scan_n));
+  const size_t bin_end = o;
+  o = region;
+  L.max_items = plan_max_items(n, c);
+  L.pencil_counts = take(4 * (size_t)r.pencils_total);
+  L.item_base = take(4 * (size_t)(r.pencils_total + 1));
+  L.items = take(sizeof(int4) * (size_t)L.max_items);
+  L.item_bucket = take(4 * (size_t)L.max_items);
+  L.queue = take(4 * (size_t)L.max_items);
+  L.ctrl = take(4 * (size_t)(3 * kBuckets + 8));
+  L.plan_scan = take(4 * (size_t)scan_tmp_ints(r.pencils_total));
+  L.mom = take(sizeof(double) * 4 * kMomChunks * r.boxes.size());
+  L.src_w = take(2 * sizeof(float4) * (size_t)n);
+  const size_t force_end = o;
+  L.total = bin_end > force_end ? bin_end : force_end;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+int check_ws(void* ws, size_t ws_bytes, const Layout& L) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
+    return ABACUS_NF_EWORKSPACE;
+  return ABACUS_NF_OK;
+}
+
+int acc_mode(uint32_t flags, AccMode* mode) {
+  const uint32_t known = ABACUS_NF_SINGLE_ACC | ABACUS_NF_CHUNKED | ABACUS_NF_COMPENSATED |
+                         ABACUS_NF_COUNT_PAIRS;
+  if (flags & ~known) return ABACUS_NF_EINVAL;
+  const uint32_t acc = flags & (ABACUS_NF_SINGLE_ACC | ABACUS_NF_CHUNKED | ABACUS_NF_COMPENSATED);
+  if (acc == 0 || acc == ABACUS_NF_COMPENSATED) *mode = kAccCompensated;
+  else if (acc == ABACUS_NF_CHUNKED) *mode = kAccChunked;
+  else if (acc == ABACUS_NF_SINGLE_ACC) *mode = kAccSingle;
+  else return ABACUS_NF_EINVAL;
+  return ABACUS_NF_OK;
+}
+
+// ---- measurement hooks ----------------------------------------------------
+struct TimedLaunch {
+  int kernel;
+  hipEvent_t start, stop;
+};
+std::mutex g_timing_mu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_pending;
+double g_ms[4] = {0, 0, 0, 0};
+int64_t g_launches[4] = {0, 0, 0, 0};
+
+struct Timer {
+  int kernel;
+  hipStream_t stream;
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool on = false;
+  Timer(int k, hipStream_t s) : kernel(k), stream(s) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    if (!g_timing) return;
+    if (hipEventCreate(&start) != hipSuccess || hipEventCreate(&stop) != hipSuccess) return;
+    on = hipEventRecord(start, stream) == hipSuccess;
+  }
+  void done() {
+    if (!on) return;
+    if (hipEventRecord(stop, stream) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    g_pending.push_back({kernel, start, stop});
+    on = false;
+  }
+};
+
+void drain_timing() {
+  for (auto& t : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.stop) == hipSuccess &&
+        hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+      g_ms[t.kernel] += ms;
+      g_launches[t.kernel] += 1;
+    }
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  g_pending.clear();
+}
+
+PlanWork plan_work(void* ws, const Layout& L) {
+  PlanWork w;
+  w.pencil_counts = at<int32_t>(ws, L.pencil_counts);
+  w.item_base = at<int32_t>(ws, L.item_base);
+  w.items = at<int4>(ws, L.items);
+  w.item_bucket = at<int32_t>(ws, L.item_bucket);
+  w.queue = at<int32_t>(ws, L.queue);
+  w.ctrl = at<int32_t>(ws, L.ctrl);
+  w.scan_tmp = at<int32_t>(ws, L.plan_scan);
+  w.max_items = L.max_items;
+  return w;
+}
+
+bool binned_ok(const abacus_nf_binned* b) {
+  return b && b->cell_offsets && b->perm && b->rel && b->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int abacus_nf_layout(const abacus_nf_box* boxes, int nboxes, int64_t* n_total,
+                     int64_t* cells_total) {
+  Resolved r;
+  const int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  if (n_total) *n_total = r.n_total;
+  if (cells_total) *cells_total = r.cells_total;
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_workspace_bytes(const abacus_nf_box* boxes, int nboxes, size_t* bytes) {
+  if (!bytes) return ABACUS_NF_EINVAL;
+  Resolved r;
+  const int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  *bytes = layout(r).total;
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_bin(const abacus_nf_box* boxes, int nboxes, const float* pos,
+                  const abacus_nf_binned* out, void* ws, size_t ws_bytes, void* stream) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  if (!binned_ok(out) || (r.n_total > 0 && !pos)) return ABACUS_NF_EINVAL;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  BinWork w;
+  w.counts = at<int32_t>(ws, L.counts);
+  w.keys[0] = at<int32_t>(ws, L.keys0);
+  w.keys[1] = at<int32_t>(ws, L.keys1);
+  w.vals[0] = at<int32_t>(ws, L.vals0);
+  w.vals[1] = at<int32_t>(ws, L.vals1);
+  w.hist = at<int32_t>(ws, L.hist);
+  w.hist_scan = at<int32_t>(ws, L.hist_scan);
+  w.scan_tmp = at<int32_t>(ws, L.bin_scan);
+  Timer t(2, s);
+  ANF_HIP(launch_bin(dboxes, nboxes, r.n_total, r.cells_total, pos, out, w, s), "binning");
+  t.done();
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                     float* acc, double* momentum, int64_t* pair_count, uint32_t flags, void* ws,
+                     size_t ws_bytes, void* stream) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  AccMode mode;
+  if ((rc = acc_mode(flags, &mode))) return rc;
+  const bool count = (flags & ABACUS_NF_COUNT_PAIRS) != 0;
+  if (!binned_ok(b) || (r.n_total > 0 && !acc) || (count && !pair_count)) return ABACUS_NF_EINVAL;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  if (count) ANF_HIP(fill_i64(pair_count, 0, 1, s), "pair counter");
+  const PlanWork w = plan_work(ws, L);
+  {
+    Timer t(3, s);
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, w, s), "work plan");
+    t.done();
+  }
+  if (r.n_total > 0) {
+    Timer t(0, s);
+    ANF_HIP(launch_forward(mode, count, dboxes, w, r.pencils_total, b->cell_offsets, b->rel,
+                           b->perm, acc, pair_count, s),
+            "forward pair kernel");
+    t.done();
+  }
+  if (momentum)
+    ANF_HIP(launch_momentum(dboxes, nboxes, r.max_box_n, acc, at<double>(ws, L.mom), momentum, s),
+            "momentum reduction");
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                         const float* wv, float* grad, uint32_t flags, void* ws, size_t ws_bytes,
+                         void* stream) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  AccMode mode;
+  if ((rc = acc_mode(flags, &mode))) return rc;
+  if (flags & ABACUS_NF_COUNT_PAIRS) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b) || (r.n_total > 0 && (!wv || !grad))) return ABACUS_NF_EINVAL;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  const PlanWork w = plan_work(ws, L);
+  {
+    Timer t(3, s);
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, w, s), "work plan");
+    t.done();
+  }
+  if (r.n_total > 0) {
+    Timer t(1, s);
+    ANF_HIP(launch_vjp(mode, dboxes, w, r.pencils_total, b->cell_offsets, b->rel, b->perm, wv,
+                       at<float4>(ws, L.src_w), r.n_total, grad, s),
+            "adjoint pair kernel");
+    t.done();
+  }
+  return ABACUS_NF_OK;
+}
+
+const char* abacus_nf_strerror(int code) {
+  switch (code) {
+    case ABACUS_NF_OK: return "ok";
+    case ABACUS_NF_EINVAL: return "invalid argument";
+    case ABACUS_NF_ERANGE: return "size out of range (particles or cells reach 2^31)";
+    case ABACUS_NF_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case ABACUS_NF_EHIP: {
+      thread_local std::string msg;
+      msg = "HIP error: " + g_last_hip_error;
+      return msg.c_str();
+    }
+    default: return "unknown error code";
+  }
+}
+
+int abacus_nf_timing_enable(int enable) {
+  std::lock_guard<std::mutex> lock(g_timing_mu);
+  g_timing = enable != 0;
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_timing_read(int kernel, double* ms, int64_t* launches) {
+  if (kernel < 0 || kernel > 3) return ABACUS_NF_EINVAL;
+  std::lock_guard<std::mutex> lock(g_timing_mu);
+  drain_timing();
+  if (ms) *ms = g_ms[kernel];
+  if (launches) *launches = g_launches[kernel];
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_timing_reset(void) {
+  std::lock_guard<std::mutex> lock(g_timing_mu);
+  drain_timing();
+  for (int k = 0; k < 4; ++k) {
+    g_ms[k] = 0.0;
+    g_launches[k] = 0;
+  }
+  return ABACUS_NF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+// Cell binning: FP64 cell assignment, per-cell counts, a stable LSD radix sort
+// of (cell, particle) and the gather of FP32 cell-relative offsets.
+//
+// Sec. 2.2: particles live on a K^3 grid of cells, slabs along x, pencils
+// along z, so the linear cell id is (x K + y) K + z.  Sec. 3.5.1: positions are
+// kept as FP32 offsets from their cell centre.  The sort is stable (ascending
+// original index inside a cell), which makes the sorted order unique and the
+// binning bit-reproducible.
+//
+// All arithmetic that decides a cell or an offset is FP64 and written as single
+// IEEE operations (this file is built without FP contraction):
+//   t = x * (K/L);  c = floor(t) mod K;  offset = (float)(t - (floor(t) + 0.5)).
+#include "nf_internal.h"
+
+namespace anf {
+
+// |t| must stay below 2^30 so the unwrapped cell fits comfortably in int32.
+constexpr double kMaxCellCoord = 1073741824.0;
+
+struct CellCoord {
+  int c;        // periodic cell index in [0, K)
+  float off;    // offset from the cell centre, cell units
+  bool ok;
+};
+
+__device__ __forceinline__ CellCoord cell_coord(float x, double cpl, int K) {
+  CellCoord r;
+  const double t = (double)x * cpl;
+  r.ok = (t == t) && fabs(t) < kMaxCellCoord;  // false for NaN, +-inf, huge
+  if (!r.ok) { r.c = 0; r.off = 0.0f; return r; }
+  const double fl = floor(t);
+  int c = (int)fl % K;
+  if (c < 0) c += K;
+  r.c = c;
+  r.off = (float)(t - (fl + 0.5));
+  return r;
+}
+
+// Pass 1: global cell id per particle, key/value init, per-cell counts.
+__global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ boxes, int nboxes,
+                                                    int64_t n_total, const float* __restrict__ pos,
+                                                    int32_t* __restrict__ keys,
+                                                    int32_t* __restrict__ vals,
+                                                    int32_t* __restrict__ counts,
+                                                    int32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_total) return;
+  const int b = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, i);
+  const double cpl = boxes[b].cells_per_len;
+  const int K = boxes[b].K;
+  const CellCoord x = cell_coord(pos[3 * i + 0], cpl, K);
+  const CellCoord y = cell_coord(pos[3 * i + 1], cpl, K);
+  const CellCoord z = cell_coord(pos[3 * i + 2], cpl, K);
+  if (!(x.ok && y.ok && z.ok)) atomicOr(status, ABACUS_NF_STATUS_BADPOS);
+  const int cell = boxes[b].cell_base + (x.c * K + y.c) * K + z.c;
+  keys[i] = cell;
+  vals[i] = (int32_t)i;
+  atomicAdd(&counts[cell], 1);
+}
+
+// Radix pass, step 1: per-block digit histogram, stored digit-major so that one
+// exclusive scan gives every (digit, block) its first output slot.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const int32_t* __restrict__ keys,
+                                                              int64_t n, int shift,
+                                                              int32_t* __restrict__ hist,
+                                                              int nblocks) {
+  __shared__ int h[256];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+  for (int k = 0; k < kRadixItems; ++k) {
+    const int64_t i = base + (int64_t)k * kRadixThreads + t;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
+}
+
+// Radix pass, step 2: stable scatter.  The block walks its keys in index order,
+// 256 at a time; inside a wave the rank of a key among equal digits comes from
+// eight ballots, across waves from per-wave digit counts in LDS.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
+    const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n, int shift,
+    const int32_t* __restrict__ hist_scan, int nblocks, int32_t* __restrict__ keys_out,
+    int32_t* __restrict__ vals_out) {
+  constexpr int kWaves = kRadixThreads / 64;
+  __shared__ int base[256];
+  __shared__ int wcount[kWaves][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  base[t] = hist_scan[(int64_t)t * nblocks + blockIdx.x];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t block0 = (int64_t)blockIdx.x * kRadixTile;
+  for (int k = 0; k < kRadixItems; ++k) {
+    for (int w = 0; w < kWaves; ++w) wcount[w][t] = 0;
+    __syncthreads();
+    const int64_t i = block0 + (int64_t)k * kRadixThreads + t;
+    const bool valid = i < n;
+    int key = 0, val = 0, d = 0;
+    if (valid) {
+      key = keys_in[i];
+      val = vals_in[i];
+      d = (key >> shift) & 255;
+    }
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    if (valid && rank == 0) wcount[wv][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = base[d] + rank;
+      for (int w = 0; w < wv; ++w) pos += wcount[w][d];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < kWaves; ++w) add += wcount[w][t];
+    base[t] += add;
+    // base[] and wcount[] are read again only after the barrier at the top
+    // of the next round.
+  }
+}
+
+// Sorted slot -> FP32 cell-relative offsets (same FP64 formula as assignment).
+__global__ __launch_bounds__(256) void k_gather_rel(const DevBox* __restrict__ boxes, int nboxes,
+                                                    int64_t n_total, const float* __restrict__ pos,
+                                                    const int32_t* __restrict__ perm,
+                                                    float4* __restrict__ rel) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_total) return;
+  const int b = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, s);
+  const double cpl = boxes[b].cells_per_len;
+  const int K = boxes[b].K;
+  const int64_t i = perm[s];
+  const CellCoord x = cell_coord(pos[3 * i + 0], cpl, K);
+  const CellCoord y = cell_coord(pos[3 * i + 1], cpl, K);
+  const CellCoord z = cell_coord(pos[3 * i + 2], cpl, K);
+  rel[s] = make_float4(x.off, y.off, z.off, 0.0f);
+}
+
+__global__ void k_iota(int32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+int64_t radix_blocks(int64_t n) { return n <= 0 ? 1 : (n + kRadixTile - 1) / kRadixTile; }
+
+static int key_bits(int64_t cells_total) {
+  int bits = 0;
+  while (bits < 31 && (int64_t(1) << bits) < cells_total) ++bits;
+  return bits;
+}
+
+#define ANF_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t cells_total,
+                      const float* pos, const abacus_nf_binned* out, const BinWork& w,
+                      hipStream_t s) {
+  ANF_TRY(fill_i32(out->status, 0, 1, s));
+  ANF_TRY(fill_i32(w.counts, 0, cells_total, s));
+  if (n_total > 0) {
+    const unsigned g = (unsigned)((n_total + 255) / 256);
+    hipLaunchKernelGGL(k_bin_assign, dim3(g), dim3(256), 0, s, boxes, nboxes, n_total, pos,
+                       w.keys[0], w.vals[0], w.counts, out->status);
+    ANF_TRY(hipGetLastError());
+  }
+  ANF_TRY(exclusive_scan(w.counts, out->cell_offsets, cells_total, w.scan_tmp, s));
+  if (n_total == 0) return hipSuccess;
+
+  const int bits = key_bits(cells_total);
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  const int nb = (int)radix_blocks(n_total);
+  const int32_t* kin = w.keys[0];
+  const int32_t* vin = w.vals[0];
+  if (passes == 0) {
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, out->perm,
+                       n_total);
+    ANF_TRY(hipGetLastError());
+  }
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * kRadixBits;
+    const bool last = p == passes - 1;
+    int32_t* kout = w.keys[(p + 1) & 1];
+    int32_t* vout = last ? out->perm : w.vals[(p + 1) & 1];
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kRadixThreads), 0, s, kin, n_total, shift,
+                       w.hist, nb);
+    ANF_TRY(hipGetLastError());
+    ANF_TRY(exclusive_scan(w.hist, w.hist_scan, (int64_t)256 * nb, w.scan_tmp, s));
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kRadixThreads), 0, s, kin, vin, n_total,
+                       shift, w.hist_scan, nb, kout, vout);
+    ANF_TRY(hipGetLastError());
+    kin = kout;
+    vin = vout;
+  }
+  hipLaunchKernelGGL(k_gather_rel, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, boxes,
+                     nboxes, n_total, pos, out->perm, reinterpret_cast<float4*>(out->rel));
+  return hipGetLastError();
+}
+
+}  // namespace anf

@@ -1,0 +1,214 @@
+// Adjoint (vector-Jacobian product) of the near-field accelerations.
+//
+// With F(d) = f(r) d (Eq. 3) the Jacobian of one pair is H(d) = f I + h d d^T,
+// h = f'(r)/r, symmetric and even in d.  For L = sum_i w_i . a_i and the
+// binning held fixed, dL/dx_k = sum_{j in NF(k)} H(d_kj) (w_j - w_k), because
+// the near-field relation is symmetric.  In cell units (d in cell widths):
+//   r >= eps:  f = r^-3,                 h = -3 r^-5
+//   r <  eps:  f = c0 + c1 r + c2 r^2,   h = ha + hb / r   (ha = 12/eps^5, hb = -15/eps^4)
+// and the box-unit gradient is the cell-unit sum times 1/w^3.
+//
+// Same traversal and work items as the forward kernel; each source carries
+// (position, cotangent) as two float4s that one wave-uniform 32-byte scalar
+// load brings into SGPRs.
+#include "nf_internal.h"
+
+namespace anf {
+
+__device__ __forceinline__ float rsq_v(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__device__ __forceinline__ void adjoint(const float4 s, const float4 ws, float qx, float qy,
+                                        float qz, float wx, float wy, float wz, float c0, float c1,
+                                        float c2, float ha, float hb, float eps, float& gx,
+                                        float& gy, float& gz) {
+  const float dx = s.x - qx;
+  const float dy = s.y - qy;
+  const float dz = s.z - qz;
+  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, kTinyR2)));
+  const float rinv = rsq_v(r2);
+  const float r = r2 * rinv;
+  const float rinv2 = rinv * rinv;
+  const float rinv3 = rinv2 * rinv;
+  const bool inner = r < eps;
+  const float f = inner ? __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0) : rinv3;
+  const float h = inner ? __builtin_fmaf(hb, rinv, ha) : (-3.0f * rinv2) * rinv3;
+  const float vx = ws.x - wx;
+  const float vy = ws.y - wy;
+  const float vz = ws.z - wz;
+  const float dv = __builtin_fmaf(dz, vz, __builtin_fmaf(dy, vy, dx * vx));
+  const float k = h * dv;
+  gx = __builtin_fmaf(k, dx, __builtin_fmaf(f, vx, gx));
+  gy = __builtin_fmaf(k, dy, __builtin_fmaf(f, vy, gy));
+  gz = __builtin_fmaf(k, dz, __builtin_fmaf(f, vz, gz));
+}
+
+__device__ __forceinline__ void two_sum_fold_v(float& a, float& e, float t) {
+  const float s = a + t;
+  const float bp = s - a;
+  const float ap = s - bp;
+  e += (a - ap) + (t - bp);
+  a = s;
+}
+
+__device__ __forceinline__ int wrap1_v(int v, int K) {
+  v += v < 0 ? K : 0;
+  v -= v >= K ? K : 0;
+  return v;
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+struct AdjConst {
+  float c0, c1, c2, ha, hb, eps;
+};
+
+__device__ __forceinline__ void sum_adjoint(const float4* __restrict__ src, int beg, int end,
+                                            float qx, float qy, float qz, float wx, float wy,
+                                            float wz, const AdjConst& k, float& gx, float& gy,
+                                            float& gz) {
+  int j = beg;
+  for (; j + 2 <= end; j += 2) {
+    const float4 s0 = src[2 * j + 0], w0 = src[2 * j + 1];
+    const float4 s1 = src[2 * j + 2], w1 = src[2 * j + 3];
+    adjoint(s0, w0, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+    adjoint(s1, w1, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+  }
+  for (; j < end; ++j)
+    adjoint(src[2 * j], src[2 * j + 1], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb,
+            k.eps, gx, gy, gz);
+}
+
+// Interleave (rel_s, w_perm[s]) per sorted slot.
+__global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ rel,
+                                                    const int32_t* __restrict__ perm,
+                                                    const float* __restrict__ w, int64_t n,
+                                                    float4* __restrict__ src) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t i = perm[s];
+  src[2 * s] = rel[s];
+  src[2 * s + 1] = make_float4(w[3 * i + 0], w[3 * i + 1], w[3 * i + 2], 0.0f);
+}
+
+template <int kAcc>
+__global__ __launch_bounds__(256) void k_pair_vjp(
+    const DevBox* __restrict__ boxes, const int4* __restrict__ items,
+    const int32_t* __restrict__ queue, const int32_t* __restrict__ n_items_ptr,
+    int32_t* __restrict__ head, const int32_t* __restrict__ off, const float4* __restrict__ src,
+    const int32_t* __restrict__ perm, float* __restrict__ grad) {
+  const int lane = threadIdx.x & 63;
+  const int n_items = uni(*n_items_ptr);
+  while (true) {
+    // Every lane takes part in the atomic (lane 0 adds 1, the others 0) so no
+    // divergent branch precedes the wave-uniform exit test below.
+    int q = atomicAdd(head, lane == 0 ? 1 : 0);
+    q = uni(__shfl(q, 0, 64));
+    if (q >= n_items) break;
+    const int4 it = items[uni(queue[q])];
+    const int b = uni(it.x);
+    const int cx = uni(it.y & 0xffff), cy = uni(it.y >> 16);
+    const int za = uni(it.z & 0xffff), zb = uni(it.z >> 16);
+    const int tile = uni(it.w);
+    const int K = uni(boxes[b].K), R = uni(boxes[b].R);
+    const int cbase = uni(boxes[b].cell_base);
+    AdjConst kc;
+    kc.c0 = boxes[b].c0; kc.c1 = boxes[b].c1; kc.c2 = boxes[b].c2;
+    kc.ha = boxes[b].ha; kc.hb = boxes[b].hb; kc.eps = boxes[b].eps;
+    const int pencil0 = cbase + (cx * K + cy) * K;
+
+    int s = -1, lane_z = za;
+    if (tile >= 0) {
+      const int c = pencil0 + za;
+      const int beg = uni(off[c]) + tile * kTile, end = uni(off[c + 1]);
+      if (beg + lane < end) s = beg + lane;
+    } else {
+      int cum = 0;
+      for (int z = za; z <= zb; ++z) {
+        const int o0 = uni(off[pencil0 + z]), o1 = uni(off[pencil0 + z + 1]);
+        const int rem = (o1 - o0) & (kTile - 1);
+        if (lane >= cum && lane < cum + rem) {
+          s = o1 - rem + (lane - cum);
+          lane_z = z;
+        }
+        cum += rem;
+      }
+    }
+    const bool active = s >= 0;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), wk = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) {
+      p = src[2 * s];
+      wk = src[2 * s + 1];
+    }
+
+    float gx = 0.f, gy = 0.f, gz = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+    for (int ox = -R; ox <= R; ++ox) {
+      const int sx = wrap1_v(cx + ox, K);
+      const float qx = p.x - (float)ox;
+      for (int oy = -R; oy <= R; ++oy) {
+        const int sy = wrap1_v(cy + oy, K);
+        const float qy = p.y - (float)oy;
+        const int col = cbase + (sx * K + sy) * K;
+        for (int zu = za - R; zu <= zb + R; ++zu) {
+          const int sz = wrap1_v(zu, K);
+          const int beg = uni(off[col + sz]), end = uni(off[col + sz + 1]);
+          if (beg == end) continue;
+          const int oz = zu - lane_z;
+          if (active && oz >= -R && oz <= R) {
+            const float qz = p.z - (float)oz;
+            if (kAcc == kAccSingle) {
+              sum_adjoint(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx, gy, gz);
+            } else {
+              for (int cb = beg; cb < end; cb += kChunk) {
+                const int ce = cb + kChunk < end ? cb + kChunk : end;
+                float tx = 0.f, ty = 0.f, tz = 0.f;
+                sum_adjoint(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx, ty, tz);
+                if (kAcc == kAccChunked) {
+                  gx += tx; gy += ty; gz += tz;
+                } else {
+                  two_sum_fold_v(gx, ex, tx);
+                  two_sum_fold_v(gy, ey, ty);
+                  two_sum_fold_v(gz, ez, tz);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    if (active) {
+      const float iw3 = boxes[b].inv_w3;
+      const int64_t i = perm[s];
+      grad[3 * i + 0] = (gx + ex) * iw3;
+      grad[3 * i + 1] = (gy + ey) * iw3;
+      grad[3 * i + 2] = (gz + ez) * iw3;
+    }
+  }
+}
+
+template <int kAcc>
+static hipError_t launch_vjp_t(const DevBox* boxes, const PlanWork& w, int64_t pencils,
+                               const int32_t* off, const float4* src, const int32_t* perm,
+                               float* grad, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_pair_vjp<kAcc>);
+  const int blocks = persistent_blocks(fn, 256);
+  hipLaunchKernelGGL((k_pair_vjp<kAcc>), dim3(blocks), dim3(256), 0, s, boxes, w.items, w.queue,
+                     w.item_base + pencils, plan_head(w), off, src, perm, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp(AccMode mode, const DevBox* boxes, const PlanWork& w, int64_t pencils,
+                      const int32_t* off, const float* rel, const int32_t* perm, const float* wvec,
+                      float4* src_w, int64_t n_total, float* grad, hipStream_t s) {
+  if (n_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_src, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(rel), perm, wvec, n_total, src_w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (mode) {
+    case kAccSingle: return launch_vjp_t<kAccSingle>(boxes, w, pencils, off, src_w, perm, grad, s);
+    case kAccChunked: return launch_vjp_t<kAccChunked>(boxes, w, pencils, off, src_w, perm, grad, s);
+    default: return launch_vjp_t<kAccCompensated>(boxes, w, pencils, off, src_w, perm, grad, s);
+  }
+}
+
+}  // namespace anf

@@ -1,0 +1,198 @@
+"""PyTorch-facing API of the near-field force.
+
+PyTorch supplies device memory and the stream; every computation is one of the
+library's HIP kernels, reached through the C ABI in ``_lib``.
+
+    spec = BoxSpec(n, box=1.0, cpd=32, radius=2, eps_plummer=1/5120)
+    nf = NearField([spec])                  # resolves sizes, owns the workspace
+    binned = nf.bin(pos)                    # pos: (n, 3) float32 on the GPU
+    acc = nf.forces(binned)                 # (n, 3) float32, original order
+    grad = nf.forces_vjp(binned, w)         # d/dpos sum(w * acc)
+
+    acc = near_field(pos, 1.0, 32, 2, 1/5120)   # autograd.Function form
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+
+
+@dataclasses.dataclass(frozen=True)
+class BoxSpec:
+    """One periodic box: n particles, side ``box``, ``cpd`` cells per dimension,
+    near-field radius ``radius`` (cells) and Plummer-equivalent softening."""
+    n: int
+    box: float
+    cpd: int
+    radius: int
+    eps_plummer: float
+
+    def astuple(self):
+        return (self.n, self.box, self.cpd, self.radius, self.eps_plummer)
+
+
+ACCUMULATION = {"compensated": _lib.COMPENSATED, "chunked": _lib.CHUNKED,
+                "single": _lib.SINGLE_ACC}
+
+
+@dataclasses.dataclass
+class Binned:
+    """Device arrays produced by ``NearField.bin`` (see include/abacus_nf.h)."""
+    cell_offsets: torch.Tensor   # int32, cells_total + 1
+    perm: torch.Tensor           # int32, n_total
+    rel: torch.Tensor            # float32, n_total x 4
+    status: torch.Tensor         # int32, 1
+
+    def cstruct(self) -> _lib.Binned:
+        return _lib.Binned(self.cell_offsets.data_ptr(), self.perm.data_ptr(),
+                           self.rel.data_ptr(), self.status.data_ptr())
+
+    def check_status(self) -> None:
+        """Raise if the binning flagged bad coordinates (synchronises)."""
+        st = int(self.status.item())
+        if st & _lib.STATUS_BADPOS:
+            raise ValueError("non-finite or out-of-range particle coordinate (|x K/L| >= 2^30)")
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class NearField:
+    """Resolved box list plus a reusable device workspace."""
+
+    def __init__(self, boxes: Sequence[BoxSpec], device=None):
+        lib = _lib.load()
+        self.specs: List[BoxSpec] = list(boxes)
+        self._boxes = _lib.box_array([b.astuple() for b in self.specs])
+        self.nboxes = len(self.specs)
+        n_total, cells_total = ctypes.c_int64(0), ctypes.c_int64(0)
+        _lib.check(lib.abacus_nf_layout(self._boxes, self.nboxes, ctypes.byref(n_total),
+                                        ctypes.byref(cells_total)), "abacus_nf_layout")
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(lib.abacus_nf_workspace_bytes(self._boxes, self.nboxes, ctypes.byref(nbytes)),
+                   "abacus_nf_workspace_bytes")
+        self.n_total = int(n_total.value)
+        self.cells_total = int(cells_total.value)
+        self.workspace_bytes = int(nbytes.value)
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self._lib = lib
+
+    # -- helpers -----------------------------------------------------------
+    def _check_pos(self, pos: torch.Tensor):
+        if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
+            raise ValueError("positions must be an (n, 3) float32 tensor")
+        if pos.shape[0] != self.n_total:
+            raise ValueError(f"expected {self.n_total} particles, got {pos.shape[0]}")
+        if pos.device != self.device or not pos.is_contiguous():
+            raise ValueError("positions must be contiguous on the workspace's device")
+
+    def alloc_binned(self) -> Binned:
+        d = self.device
+        return Binned(torch.empty(self.cells_total + 1, dtype=torch.int32, device=d),
+                      torch.empty(self.n_total, dtype=torch.int32, device=d),
+                      torch.empty((self.n_total, 4), dtype=torch.float32, device=d),
+                      torch.empty(1, dtype=torch.int32, device=d))
+
+    # -- entry points --------------------------------------------------------
+    def bin(self, pos: torch.Tensor, out: Optional[Binned] = None, check: bool = False) -> Binned:
+        self._check_pos(pos)
+        out = out if out is not None else self.alloc_binned()
+        cs = out.cstruct()
+        _lib.check(self._lib.abacus_nf_bin(self._boxes, self.nboxes, _ptr(pos), ctypes.byref(cs),
+                                           _ptr(self.workspace), self.workspace_bytes, _stream()),
+                   "abacus_nf_bin")
+        if check:
+            out.check_status()
+        return out
+
+    def forces(self, binned: Binned, accumulation: str = "compensated",
+               out: Optional[torch.Tensor] = None, momentum: bool = False,
+               count_pairs: bool = False, momentum_out: Optional[torch.Tensor] = None,
+               pairs_out: Optional[torch.Tensor] = None
+               ) -> Tuple[torch.Tensor, Optional[torch.Tensor], Optional[torch.Tensor]]:
+        """Accelerations (n, 3) in original order; optionally the per-box FP64
+        momentum sums (nboxes, 4) and the evaluated pair count (1,) int64."""
+        flags = ACCUMULATION[accumulation] | (_lib.COUNT_PAIRS if count_pairs else 0)
+        acc = out if out is not None else torch.empty((self.n_total, 3), dtype=torch.float32,
+                                                      device=self.device)
+        mom = momentum_out
+        if mom is None and momentum:
+            mom = torch.empty((self.nboxes, 4), dtype=torch.float64, device=self.device)
+        pairs = pairs_out
+        if pairs is None and count_pairs:
+            pairs = torch.empty(1, dtype=torch.int64, device=self.device)
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_forces(self._boxes, self.nboxes, ctypes.byref(cs), _ptr(acc),
+                                              _ptr(mom), _ptr(pairs), flags, _ptr(self.workspace),
+                                              self.workspace_bytes, _stream()),
+                   "abacus_nf_forces")
+        return acc, mom, pairs
+
+    def forces_vjp(self, binned: Binned, w: torch.Tensor, accumulation: str = "compensated",
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if w.dtype != torch.float32 or tuple(w.shape) != (self.n_total, 3) or not w.is_contiguous():
+            raise ValueError("cotangent must be a contiguous (n, 3) float32 tensor")
+        grad = out if out is not None else torch.empty((self.n_total, 3), dtype=torch.float32,
+                                                       device=self.device)
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_forces_vjp(self._boxes, self.nboxes, ctypes.byref(cs),
+                                                  _ptr(w), _ptr(grad), ACCUMULATION[accumulation],
+                                                  _ptr(self.workspace), self.workspace_bytes,
+                                                  _stream()),
+                   "abacus_nf_forces_vjp")
+        return grad
+
+
+class _NearFieldFn(torch.autograd.Function):
+    """acc = near-field accelerations of pos; backward is the hand-written adjoint
+    kernel on the binning saved by forward (binning is piecewise constant in pos,
+    so it contributes no gradient)."""
+
+    @staticmethod
+    def forward(ctx, pos, nf: NearField, accumulation: str):
+        binned = nf.bin(pos.contiguous())
+        acc, _, _ = nf.forces(binned, accumulation)
+        ctx.nf = nf
+        ctx.binned = binned
+        ctx.accumulation = accumulation
+        return acc
+
+    @staticmethod
+    def backward(ctx, grad_acc):
+        g = ctx.nf.forces_vjp(ctx.binned, grad_acc.contiguous().float(), ctx.accumulation)
+        return g, None, None
+
+
+def near_field(pos: torch.Tensor, box: float, cpd: int, radius: int, eps_plummer: float,
+               compensated: bool = True, nf: Optional[NearField] = None) -> torch.Tensor:
+    """Near-field accelerations of one periodic box, differentiable in ``pos``."""
+    if nf is None:
+        nf = NearField([BoxSpec(pos.shape[0], box, cpd, radius, eps_plummer)], device=pos.device)
+    return _NearFieldFn.apply(pos, nf, "compensated" if compensated else "chunked")
+
+
+def timing_enable(enable: bool = True) -> None:
+    _lib.check(_lib.load().abacus_nf_timing_enable(1 if enable else 0), "timing_enable")
+
+
+def timing_reset() -> None:
+    _lib.check(_lib.load().abacus_nf_timing_reset(), "timing_reset")
+
+
+def timing_read(kernel: int) -> Tuple[float, int]:
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _lib.check(_lib.load().abacus_nf_timing_read(kernel, ctypes.byref(ms), ctypes.byref(n)),
+               "timing_read")
+    return float(ms.value), int(n.value)

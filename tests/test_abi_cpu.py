@@ -1,0 +1,125 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2110_11392_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "abacus_nf.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(abacus_nf_\w+)\s*\(", text,
+                                 flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for required in ("abacus_nf_bin", "abacus_nf_forces", "abacus_nf_forces_vjp",
+                     "abacus_nf_workspace_bytes", "abacus_nf_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (abacus_nf_\w+)", out))
+    assert set(header_functions()) <= exported
+
+
+def boxes(*specs):
+    return _lib.box_array(specs)
+
+
+@pytest.mark.parametrize("spec,code", [
+    ((100, 1.0, 8, 2, 1e-3), _lib.OK),
+    ((-1, 1.0, 8, 2, 1e-3), _lib.EINVAL),
+    ((100, 0.0, 8, 2, 1e-3), _lib.EINVAL),
+    ((100, float("inf"), 8, 2, 1e-3), _lib.EINVAL),
+    ((100, float("nan"), 8, 2, 1e-3), _lib.EINVAL),
+    ((100, 1.0, 4, 2, 1e-3), _lib.EINVAL),           # K < 2R+1
+    ((100, 1.0, 5, 2, 1e-3), _lib.OK),               # K = 2R+1
+    ((100, 1.0, 8, -1, 1e-3), _lib.EINVAL),
+    ((100, 1.0, 8, 2, 0.0), _lib.EINVAL),
+    ((100, 1.0, 8, 2, float("nan")), _lib.EINVAL),
+    ((100, 1.0, 8, 2, 1e-12), _lib.EINVAL),          # softening below 1e-6 cells
+    ((2 ** 31, 1.0, 8, 2, 1e-3), _lib.ERANGE),
+    ((100, 1.0, 1300, 2, 1e-3), _lib.ERANGE),        # K^3 >= 2^31
+])
+def test_layout_validation(spec, code):
+    lib = _lib.load()
+    n, c = ctypes.c_int64(0), ctypes.c_int64(0)
+    assert lib.abacus_nf_layout(boxes(spec), 1, ctypes.byref(n), ctypes.byref(c)) == code
+    if code == _lib.OK:
+        assert n.value == spec[0] and c.value == spec[2] ** 3
+
+
+def test_layout_of_a_batch():
+    lib = _lib.load()
+    n, c = ctypes.c_int64(0), ctypes.c_int64(0)
+    b = boxes((10, 1.0, 8, 2, 1e-3), (0, 2.0, 5, 2, 1e-3), (7, 1.0, 9, 1, 1e-3))
+    assert lib.abacus_nf_layout(b, 3, ctypes.byref(n), ctypes.byref(c)) == 0
+    assert n.value == 17 and c.value == 8 ** 3 + 5 ** 3 + 9 ** 3
+    assert lib.abacus_nf_layout(b, 0, None, None) == _lib.EINVAL
+    assert lib.abacus_nf_layout(None, 1, None, None) == _lib.EINVAL
+
+
+def test_entry_points_validate_before_device_work():
+    """Every error path below returns before any HIP call, so it runs on the CPU."""
+    lib = _lib.load()
+    b = boxes((100, 1.0, 8, 2, 1e-3))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.abacus_nf_workspace_bytes(b, 1, ctypes.byref(nbytes)) == 0
+    assert nbytes.value > 0
+    assert lib.abacus_nf_workspace_bytes(b, 1, None) == _lib.EINVAL
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    nul = _lib.Binned(None, 0x1000, 0x1000, 0x1000)
+    # null positions / binned arrays
+    assert lib.abacus_nf_bin(b, 1, None, ctypes.byref(binned), fake, nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_bin(b, 1, fake, ctypes.byref(nul), fake, nbytes, None) == _lib.EINVAL
+    # workspace: null, misaligned, too small
+    assert lib.abacus_nf_bin(b, 1, fake, ctypes.byref(binned), None, nbytes, None) == \
+        _lib.EWORKSPACE
+    assert lib.abacus_nf_bin(b, 1, fake, ctypes.byref(binned), ctypes.c_void_p(0x1004), nbytes,
+                             None) == _lib.EWORKSPACE
+    assert lib.abacus_nf_bin(b, 1, fake, ctypes.byref(binned), fake, nbytes.value - 1, None) == \
+        _lib.EWORKSPACE
+    # forces: bad flags, conflicting accumulation modes, missing pair counter
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, 0x100, fake, nbytes,
+                                None) == _lib.EINVAL
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None,
+                                _lib.SINGLE_ACC | _lib.COMPENSATED, fake, nbytes, None) == \
+        _lib.EINVAL
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, _lib.COUNT_PAIRS,
+                                fake, nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), None, None, None, 0, fake, nbytes,
+                                None) == _lib.EINVAL
+    # adjoint: no pair counting, null cotangent
+    assert lib.abacus_nf_forces_vjp(b, 1, ctypes.byref(binned), fake, fake, _lib.COUNT_PAIRS, fake,
+                                    nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_forces_vjp(b, 1, ctypes.byref(binned), None, fake, 0, fake, nbytes,
+                                    None) == _lib.EINVAL
+
+
+def test_strerror_texts():
+    for code in (_lib.OK, _lib.EINVAL, _lib.ERANGE, _lib.EWORKSPACE, _lib.EHIP, -99):
+        assert isinstance(_lib.strerror(code), str) and _lib.strerror(code)
+
+
+def test_timing_hooks_without_gpu():
+    lib = _lib.load()
+    assert lib.abacus_nf_timing_reset() == 0
+    ms, n = ctypes.c_double(1.0), ctypes.c_int64(5)
+    assert lib.abacus_nf_timing_read(0, ctypes.byref(ms), ctypes.byref(n)) == 0
+    assert ms.value == 0.0 and n.value == 0
+    assert lib.abacus_nf_timing_read(7, None, None) == _lib.EINVAL

@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--accumulation", default="compensated",
                     choices=["compensated", "chunked", "single"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of timing candidates")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the extra measurement of the step replayed from a HIP graph")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -138,6 +142,14 @@ def main():
         step()
     torch.cuda.synchronize()
     binned.check_status()
+    tuning = {"forward": nf.get_tuning(0, args.accumulation),
+              "adjoint": nf.get_tuning(1, args.accumulation)}
+    if not args.no_autotune:
+        log("[bench] autotune")
+        tuning = nf.autotune(binned, args.accumulation)
+        log(f"[bench] tuned {tuning}")
+        step()
+        torch.cuda.synchronize()
     pairs = exact_pairs(binned.cell_offsets.cpu().numpy(), boxes)
     log(f"[bench] pairs per evaluation: {pairs}")
 
@@ -159,6 +171,29 @@ def main():
     kt = {name: anf.timing_read(k) for name, k in
           (("forward", 0), ("adjoint", 1), ("bin", 2), ("plan", 3))}
     avg = {name: (ms / n if n else float("nan")) for name, (ms, n) in kt.items()}
+    graph_ms = None
+    if not args.no_graph:
+        log("[bench] graph capture")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(args.steps):
+            graph.replay()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / args.steps
+        log(f"[bench] graph replay {graph_ms:.3f} ms/step")
     m = mom.cpu().numpy()
     resid = float(np.abs(m[:, :3]).max() / m[:, 3].max())
 
@@ -182,7 +217,9 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "n": nf.n_total, "pairs_per_evaluation": pairs,
                    "accumulation": args.accumulation,
-                   "step": "bin + forward(+FP64 momentum) + adjoint"},
+                   "step": "bin + forward(+FP64 momentum) + adjoint",
+                   "tuning": tuning},
+        "ms_per_step_graph_replay": graph_ms,
         "forward_gpairs_per_s": pairs / (avg["forward"] * 1e-3) / 1e9,
         "adjoint_gpairs_per_s": pairs / (avg["adjoint"] * 1e-3) / 1e9,
         "particle_updates_per_s": nf.n_total / ((avg["bin"] + avg["plan"] + avg["forward"]) * 1e-3),

@@ -155,6 +155,44 @@ int abacus_nf_forces_vjp(const abacus_nf_box *boxes, int nboxes, const abacus_nf
  * message of the last failing HIP call on this thread. */
 const char *abacus_nf_strerror(int code);
 
+/* ---- tuning of the pair kernels (a9: tile shapes chosen by measurement) --- */
+
+/* Launch shape of one pair kernel.  Every shape computes the same sums in the
+ * same order per sink: the choice changes speed, never results. */
+typedef struct {
+    int32_t unroll;     /* sources per inner-loop step: 2, 4 or 8 (adjoint: 2 or 4) */
+    int32_t pipeline;   /* 1: request the next step's sources before using the current ones */
+    int32_t span;       /* most cells one 64-sink work item spans along its pencil: 1, 2 or 3 */
+    int32_t grid_mult;  /* persistent workgroups per resident slot: 1 or 2 */
+} abacus_nf_tuning;
+
+#define ABACUS_NF_KERNEL_FORWARD 0
+#define ABACUS_NF_KERNEL_ADJOINT 1
+
+/*
+ * abacus_nf_autotune -- time candidate shapes of the forward and adjoint pair
+ * kernels on this binned input and keep the fastest for this problem shape
+ * (box list, accumulation flags, device) in a process-wide table that later
+ * abacus_nf_forces / abacus_nf_forces_vjp calls use.  The search is a
+ * coordinate descent (span, then unroll/pipeline, then grid) with two timed
+ * runs per candidate.  `scratch` is n_total x 3 FP32 device memory whose
+ * contents are overwritten.  Unlike the other entry points this call
+ * SYNCHRONISES `stream`; do not call it while capturing a graph.  If the
+ * environment variable ABACUS_NF_TUNE_CACHE names a file, results are appended
+ * to it and read back by later processes.  Either output pointer may be NULL.
+ */
+int abacus_nf_autotune(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                       float *scratch, uint32_t flags, void *ws, size_t ws_bytes, void *stream,
+                       abacus_nf_tuning *forward_out, abacus_nf_tuning *adjoint_out);
+
+/* Read or override the shape used for (boxes, flags, kernel); t == NULL in
+ * abacus_nf_set_tuning restores the built-in default.  EINVAL on shapes
+ * outside the ranges above. */
+int abacus_nf_get_tuning(const abacus_nf_box *boxes, int nboxes, uint32_t flags, int kernel,
+                         abacus_nf_tuning *out);
+int abacus_nf_set_tuning(const abacus_nf_box *boxes, int nboxes, uint32_t flags, int kernel,
+                         const abacus_nf_tuning *t);
+
 /* ---- measurement hooks (not needed for computing) ------------------------ */
 /* When enabled, the library records HIP events around its pair kernels on the
  * caller's stream; abacus_nf_timing_read returns the summed milliseconds and

@@ -35,13 +35,26 @@ class Box(ctypes.Structure):
                 ("radius", ctypes.c_int32), ("eps_plummer", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("unroll", ctypes.c_int32), ("pipeline", ctypes.c_int32),
+                ("span", ctypes.c_int32), ("grid_mult", ctypes.c_int32)]
+
+    def asdict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+KERNEL_FORWARD = 0
+KERNEL_ADJOINT = 1
+
+
 class Binned(ctypes.Structure):
     _fields_ = [("cell_offsets", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("rel", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 EXPORTS = ("abacus_nf_layout", "abacus_nf_workspace_bytes", "abacus_nf_bin", "abacus_nf_forces",
-           "abacus_nf_forces_vjp", "abacus_nf_strerror", "abacus_nf_timing_enable",
+           "abacus_nf_forces_vjp", "abacus_nf_strerror", "abacus_nf_autotune",
+           "abacus_nf_get_tuning", "abacus_nf_set_tuning", "abacus_nf_timing_enable",
            "abacus_nf_timing_read", "abacus_nf_timing_reset")
 
 _lib = None
@@ -71,6 +84,11 @@ def load() -> ctypes.CDLL:
     lib.abacus_nf_bin.argtypes = [BoxP, ctypes.c_int, vp, BinnedP, vp, sz, vp]
     lib.abacus_nf_forces.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, u32, vp, sz, vp]
     lib.abacus_nf_forces_vjp.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, u32, vp, sz, vp]
+    TuneP = ctypes.POINTER(Tuning)
+    lib.abacus_nf_autotune.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp, TuneP,
+                                       TuneP]
+    lib.abacus_nf_get_tuning.argtypes = [BoxP, ctypes.c_int, u32, ctypes.c_int, TuneP]
+    lib.abacus_nf_set_tuning.argtypes = [BoxP, ctypes.c_int, u32, ctypes.c_int, TuneP]
     lib.abacus_nf_strerror.argtypes = [ctypes.c_int]
     lib.abacus_nf_strerror.restype = ctypes.c_char_p
     lib.abacus_nf_timing_enable.argtypes = [ctypes.c_int]

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libabacus_nf.so")
 ARCH = "gfx950"
 
-SOURCES = ["common.hip", "bin.hip", "plan.hip", "pairs.hip", "vjp.hip", "reduce.hip", "api.hip"]
+SOURCES = ["common.hip", "bin.hip", "plan.hip", "pairs.hip", "vjp.hip", "reduce.hip", "tune.hip",
+           "api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

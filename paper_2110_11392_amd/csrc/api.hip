@@ -99,7 +99,7 @@ struct Layout {
   // binning region
   size_t counts, keys0, keys1, vals0, vals1, hist, hist_scan, bin_scan;
   // force / adjoint region (overlaps the binning region)
-  size_t pencil_counts, item_base, items, item_bucket, queue, ctrl, plan_scan, mom, src_w;
+  size_t pencil_counts, item_base, items, item_bucket, item_slot, queue, ctrl, plan_scan, mom, src_w;
   size_t total;
   int64_t max_items;
 };
@@ -127,11 +127,12 @@ Layout layout(const Resolved& r) {
   L.bin_scan = take(4 * (size_t)scan_tmp_ints(scan_n));
   const size_t bin_end = o;
   o = region;
-  L.max_items = plan_max_items(n, c);
+  L.max_items = plan_max_items(n, c, r.pencils_total);
   L.pencil_counts = take(4 * (size_t)r.pencils_total);
   L.item_base = take(4 * (size_t)(r.pencils_total + 1));
   L.items = take(sizeof(int4) * (size_t)L.max_items);
   L.item_bucket = take(4 * (size_t)L.max_items);
+  L.item_slot = take(4 * (size_t)L.max_items);
   L.queue = take(4 * (size_t)L.max_items);
   L.ctrl = take(4 * (size_t)(3 * kBuckets + 8));
   L.plan_scan = take(4 * (size_t)scan_tmp_ints(r.pencils_total));
@@ -163,6 +164,33 @@ int acc_mode(uint32_t flags, AccMode* mode) {
   else if (acc == ABACUS_NF_SINGLE_ACC) *mode = kAccSingle;
   else return ABACUS_NF_EINVAL;
   return ABACUS_NF_OK;
+}
+
+TuneKey tune_key(const abacus_nf_box* boxes, int nboxes, const Resolved& r, AccMode mode,
+                 int kernel) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  for (int b = 0; b < nboxes; ++b) {
+    mix(&boxes[b].n, sizeof(boxes[b].n));
+    mix(&boxes[b].box, sizeof(boxes[b].box));
+    mix(&boxes[b].cpd, sizeof(boxes[b].cpd));
+    mix(&boxes[b].radius, sizeof(boxes[b].radius));
+    mix(&boxes[b].eps_plummer, sizeof(boxes[b].eps_plummer));
+  }
+  TuneKey k;
+  k.kernel = kernel;
+  k.mode = (uint32_t)mode;
+  k.nboxes = nboxes;
+  k.n_total = r.n_total;
+  k.cells_total = r.cells_total;
+  k.shape_hash = h;
+  return k;
 }
 
 // ---- measurement hooks ----------------------------------------------------
@@ -216,6 +244,7 @@ PlanWork plan_work(void* ws, const Layout& L) {
   w.item_base = at<int32_t>(ws, L.item_base);
   w.items = at<int4>(ws, L.items);
   w.item_bucket = at<int32_t>(ws, L.item_bucket);
+  w.item_slot = at<int32_t>(ws, L.item_slot);
   w.queue = at<int32_t>(ws, L.queue);
   w.ctrl = at<int32_t>(ws, L.ctrl);
   w.scan_tmp = at<int32_t>(ws, L.plan_scan);
@@ -293,14 +322,16 @@ int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_bin
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
   if (count) ANF_HIP(fill_i64(pair_count, 0, 1, s), "pair counter");
   const PlanWork w = plan_work(ws, L);
+  const KernelConfig cfg = lookup_config(tune_key(boxes, nboxes, r, mode, 0));
   {
     Timer t(3, s);
-    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, w, s), "work plan");
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, w, s),
+            "work plan");
     t.done();
   }
   if (r.n_total > 0) {
     Timer t(0, s);
-    ANF_HIP(launch_forward(mode, count, dboxes, w, r.pencils_total, b->cell_offsets, b->rel,
+    ANF_HIP(launch_forward(mode, count, cfg, dboxes, w, r.pencils_total, b->cell_offsets, b->rel,
                            b->perm, acc, pair_count, s),
             "forward pair kernel");
     t.done();
@@ -327,18 +358,160 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   DevBox* dboxes = at<DevBox>(ws, L.boxtab);
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
   const PlanWork w = plan_work(ws, L);
+  const KernelConfig cfg = lookup_config(tune_key(boxes, nboxes, r, mode, 1));
   {
     Timer t(3, s);
-    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, w, s), "work plan");
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, w, s),
+            "work plan");
     t.done();
   }
   if (r.n_total > 0) {
     Timer t(1, s);
-    ANF_HIP(launch_vjp(mode, dboxes, w, r.pencils_total, b->cell_offsets, b->rel, b->perm, wv,
+    ANF_HIP(launch_vjp(mode, cfg, dboxes, w, r.pencils_total, b->cell_offsets, b->rel, b->perm, wv,
                        at<float4>(ws, L.src_w), r.n_total, grad, s),
             "adjoint pair kernel");
     t.done();
   }
+  return ABACUS_NF_OK;
+}
+
+static abacus_nf_tuning to_public(const KernelConfig& c) {
+  abacus_nf_tuning t;
+  t.unroll = c.unroll;
+  t.pipeline = c.pipeline;
+  t.span = c.span;
+  t.grid_mult = c.grid_mult;
+  return t;
+}
+
+static KernelConfig from_public(const abacus_nf_tuning& t) {
+  KernelConfig c;
+  c.unroll = t.unroll;
+  c.pipeline = t.pipeline;
+  c.span = t.span;
+  c.grid_mult = t.grid_mult;
+  return c;
+}
+
+int abacus_nf_get_tuning(const abacus_nf_box* boxes, int nboxes, uint32_t flags, int kernel,
+                         abacus_nf_tuning* out) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  AccMode mode;
+  if ((rc = acc_mode(flags & ~ABACUS_NF_COUNT_PAIRS, &mode))) return rc;
+  if (!out || (kernel != 0 && kernel != 1)) return ABACUS_NF_EINVAL;
+  *out = to_public(lookup_config(tune_key(boxes, nboxes, r, mode, kernel)));
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_set_tuning(const abacus_nf_box* boxes, int nboxes, uint32_t flags, int kernel,
+                         const abacus_nf_tuning* t) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  AccMode mode;
+  if ((rc = acc_mode(flags & ~ABACUS_NF_COUNT_PAIRS, &mode))) return rc;
+  if (kernel != 0 && kernel != 1) return ABACUS_NF_EINVAL;
+  const TuneKey key = tune_key(boxes, nboxes, r, mode, kernel);
+  if (!t) {
+    clear_config(key);
+    return ABACUS_NF_OK;
+  }
+  const KernelConfig c = from_public(*t);
+  if (!config_valid(kernel, c)) return ABACUS_NF_EINVAL;
+  store_config(key, c, false);
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                       float* scratch, uint32_t flags, void* ws, size_t ws_bytes, void* stream,
+                       abacus_nf_tuning* forward_out, abacus_nf_tuning* adjoint_out) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  AccMode mode;
+  if ((rc = acc_mode(flags, &mode))) return rc;
+  if (flags & ABACUS_NF_COUNT_PAIRS) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b) || (r.n_total > 0 && !scratch)) return ABACUS_NF_EINVAL;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const TuneKey kf = tune_key(boxes, nboxes, r, mode, 0), ka = tune_key(boxes, nboxes, r, mode, 1);
+  KernelConfig best[2] = {default_config(0), default_config(1)};
+  if (r.n_total > 0) {
+    DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+    ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+    const PlanWork w = plan_work(ws, L);
+    hipEvent_t e0, e1;
+    ANF_HIP(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return hip_fail(hipErrorOutOfMemory, "event");
+    }
+    hipError_t err = hipSuccess;
+    // Time plan + kernel: one warm-up, then the best of two.
+    auto run = [&](int kernel, const KernelConfig& c) -> float {
+      float best_ms = 3.0e38f;
+      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess)
+          err = launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, c.span, w, s);
+        if (err == hipSuccess) {
+          if (kernel == 0)
+            err = launch_forward(mode, false, c, dboxes, w, r.pencils_total, b->cell_offsets,
+                                 b->rel, b->perm, scratch, nullptr, s);
+          else  // any finite cotangent times the same: read the offsets as w
+            err = launch_vjp(mode, c, dboxes, w, r.pencils_total, b->cell_offsets, b->rel,
+                             b->perm, b->rel, at<float4>(ws, L.src_w), r.n_total, scratch, s);
+        }
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && ms < best_ms) best_ms = ms;
+      }
+      return best_ms;
+    };
+    for (int kernel = 0; kernel < 2 && err == hipSuccess; ++kernel) {
+      KernelConfig cur = default_config(kernel);
+      float t_cur = run(kernel, cur);
+      auto try_cfg = [&](const KernelConfig& c) {
+        if (!config_valid(kernel, c) || err != hipSuccess) return;
+        const float t = run(kernel, c);
+        if (t < t_cur) {
+          t_cur = t;
+          cur = c;
+        }
+      };
+      for (int span = 1; span <= kMaxSpan; ++span) {
+        KernelConfig c = cur;
+        c.span = span;
+        try_cfg(c);
+      }
+      const KernelConfig base = cur;
+      for (int u : {2, 4, 8})
+        for (int pipe = 0; pipe < 2; ++pipe) {
+          KernelConfig c = base;
+          c.unroll = u;
+          c.pipeline = pipe;
+          try_cfg(c);
+        }
+      {
+        KernelConfig c = cur;
+        c.grid_mult = 3 - cur.grid_mult;
+        try_cfg(c);
+      }
+      best[kernel] = cur;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err, "autotune");
+  }
+  store_config(kf, best[0], true);
+  store_config(ka, best[1], true);
+  if (forward_out) *forward_out = to_public(best[0]);
+  if (adjoint_out) *adjoint_out = to_public(best[1]);
   return ABACUS_NF_OK;
 }
 

@@ -16,8 +16,10 @@ constexpr int kTile = 64;
 // Largest number of sources summed into one FP32 partial before it is folded
 // into the sink's accumulator (CHUNKED / COMPENSATED accumulation).
 constexpr int kChunk = 64;
-// Most cells whose partial tiles are packed into one work item (pencil segment).
-constexpr int kMaxPack = 4;
+// Most cells one work item's 64 sinks may span along its pencil (the planner's
+// span parameter is 1..kMaxSpan; kDefaultSpan unless the autotuner chose another).
+constexpr int kMaxSpan = 3;
+constexpr int kDefaultSpan = 2;
 // Cost buckets for the longest-first work queue (floor(log2 cost) descending).
 constexpr int kBuckets = 64;
 // Radix sort: 8-bit digits, 256 threads x 16 keys per block.
@@ -111,31 +113,55 @@ struct PlanWork {
   int32_t* pencil_counts;  // pencils_total
   int32_t* item_base;      // pencils_total + 1 (item_base[pencils_total] = item count)
   int4* items;             // max_items
-  int32_t* item_bucket;    // max_items
+  int32_t* item_bucket;    // max_items: cost bucket of each item
+  int32_t* item_slot;      // max_items: position of the item inside its bucket
   int32_t* queue;          // max_items
   int32_t* ctrl;           // kBuckets*3 + 8: counts, bases, cursors, head
   int32_t* scan_tmp;
   int64_t max_items;
 };
-int64_t plan_max_items(int64_t n_total, int64_t cells_total);
+int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_total);
 hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils_total,
-                       const int32_t* cell_offsets, const PlanWork& w, hipStream_t s);
+                       const int32_t* cell_offsets, int span, const PlanWork& w, hipStream_t s);
 inline int32_t* plan_head(const PlanWork& w) { return w.ctrl + 3 * kBuckets; }
 inline const int32_t* plan_n_items(const PlanWork& w, int64_t pencils_total) {
   return w.item_base + pencils_total;
 }
 
+// Tunable launch shape of a pair kernel (chosen by the autotuner in tune.hip).
+struct KernelConfig {
+  int unroll;     // sources per step of the inner loop (2, 4 or 8)
+  int pipeline;   // 1: request the next step's sources before using the current ones
+  int span;       // most cells one work item may span (1..3); a planner parameter
+  int grid_mult;  // persistent workgroups per resident slot (1 or 2)
+};
+KernelConfig default_config(int kernel);  // kernel 0: forward, 1: adjoint
+bool config_valid(int kernel, const KernelConfig& c);
+
+// Problem signature under which a tuned shape is stored (tune.hip).
+struct TuneKey {
+  int kernel;           // 0 forward, 1 adjoint
+  uint32_t mode;        // accumulation flags
+  int nboxes;
+  int64_t n_total, cells_total;
+  uint64_t shape_hash;  // FNV-1a over the box list
+};
+KernelConfig lookup_config(const TuneKey& k);
+void store_config(const TuneKey& k, const KernelConfig& c, bool persist);
+void clear_config(const TuneKey& k);
+
 // pairs.hip
 enum AccMode { kAccSingle = 0, kAccChunked = 1, kAccCompensated = 2 };
-hipError_t launch_forward(AccMode mode, bool count_pairs, const DevBox* boxes, const PlanWork& w,
-                          int64_t pencils_total, const int32_t* cell_offsets, const float* rel,
-                          const int32_t* perm, float* acc, int64_t* pair_count, hipStream_t s);
+hipError_t launch_forward(AccMode mode, bool count_pairs, const KernelConfig& cfg,
+                          const DevBox* boxes, const PlanWork& w, int64_t pencils_total,
+                          const int32_t* cell_offsets, const float* rel, const int32_t* perm,
+                          float* acc, int64_t* pair_count, hipStream_t s);
 
 // vjp.hip
-hipError_t launch_vjp(AccMode mode, const DevBox* boxes, const PlanWork& w, int64_t pencils_total,
-                      const int32_t* cell_offsets, const float* rel, const int32_t* perm,
-                      const float* wvec, float4* src_w, int64_t n_total, float* grad,
-                      hipStream_t s);
+hipError_t launch_vjp(AccMode mode, const KernelConfig& cfg, const DevBox* boxes,
+                      const PlanWork& w, int64_t pencils_total, const int32_t* cell_offsets,
+                      const float* rel, const int32_t* perm, const float* wvec, float4* src_w,
+                      int64_t n_total, float* grad, hipStream_t s);
 
 // reduce.hip
 hipError_t launch_momentum(const DevBox* boxes, int nboxes, int64_t max_box_n, const float* acc,

@@ -59,25 +59,42 @@ __device__ __forceinline__ int wrap1(int v, int K) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Sum the sources [beg, end) into (tx, ty, tz), four per step.
+// Sum the sources [beg, end) into (tx, ty, tz), kU per step.  With kPipe the
+// next kU sources are requested before the current ones are used, so the
+// scalar-cache latency of one group overlaps the arithmetic of the previous.
+template <int kU, bool kPipe>
 __device__ __forceinline__ void sum_sources(const float4* __restrict__ rel, int beg, int end,
                                             float qx, float qy, float qz, float c0, float c1,
                                             float c2, float& tx, float& ty, float& tz) {
   int j = beg;
-  for (; j + 4 <= end; j += 4) {
-    const float4 s0 = rel[j + 0];
-    const float4 s1 = rel[j + 1];
-    const float4 s2 = rel[j + 2];
-    const float4 s3 = rel[j + 3];
-    interact(s0, qx, qy, qz, c0, c1, c2, tx, ty, tz);
-    interact(s1, qx, qy, qz, c0, c1, c2, tx, ty, tz);
-    interact(s2, qx, qy, qz, c0, c1, c2, tx, ty, tz);
-    interact(s3, qx, qy, qz, c0, c1, c2, tx, ty, tz);
+  if (kPipe && j + kU <= end) {
+    float4 cur[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) cur[u] = rel[j + u];
+    for (; j + 2 * kU <= end; j += kU) {
+      float4 nxt[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) nxt[u] = rel[j + kU + u];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) interact(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) interact(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+    j += kU;
+  }
+  for (; j + kU <= end; j += kU) {
+    float4 cur[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) cur[u] = rel[j + u];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) interact(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
   }
   for (; j < end; ++j) interact(rel[j], qx, qy, qz, c0, c1, c2, tx, ty, tz);
 }
 
-template <int kAcc, bool kCount>
+template <int kAcc, bool kCount, int kU, bool kPipe>
 __global__ __launch_bounds__(256) void k_pair_forward(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
     const int32_t* __restrict__ queue, const int32_t* __restrict__ n_items_ptr,
@@ -93,33 +110,25 @@ __global__ __launch_bounds__(256) void k_pair_forward(
     q = uniform(__shfl(q, 0, 64));
     if (q >= n_items) break;
     const int4 it = items[uniform(queue[q])];
-    const int b = uniform(it.x);
+    const int b = uniform(it.x & 0xffff), count = uniform(it.x >> 16);
     const int cx = uniform(it.y & 0xffff), cy = uniform(it.y >> 16);
     const int za = uniform(it.z & 0xffff), zb = uniform(it.z >> 16);
-    const int tile = uniform(it.w);
+    const int first = uniform(it.w);
     const int K = uniform(boxes[b].K), R = uniform(boxes[b].R);
     const int cbase = uniform(boxes[b].cell_base);
-    const float c0 = boxes[b].c0, c1 = boxes[b].c1, c2 = boxes[b].c2;
+    const float c0 = boxes[b].c0, c2 = boxes[b].c2;
+    // c1 meets an SGPR operand (c2) in the spline FMA; a VALU instruction reads
+    // at most one SGPR, so keep c1 in a VGPR for the whole item.
+    float c1 = boxes[b].c1;
+    asm volatile("" : "+v"(c1));
     const int pencil0 = cbase + (cx * K + cy) * K;
 
     // ---- which sink this lane owns -------------------------------------
-    int s = -1, lane_z = za;
-    if (tile >= 0) {
-      const int c = pencil0 + za;
-      const int beg = uniform(off[c]) + tile * kTile, end = uniform(off[c + 1]);
-      if (beg + lane < end) s = beg + lane;
-    } else {
-      int cum = 0;
-      for (int z = za; z <= zb; ++z) {
-        const int o0 = uniform(off[pencil0 + z]), o1 = uniform(off[pencil0 + z + 1]);
-        const int rem = (o1 - o0) & (kTile - 1);
-        if (lane >= cum && lane < cum + rem) {
-          s = o1 - rem + (lane - cum);
-          lane_z = z;
-        }
-        cum += rem;
-      }
-    }
+    // lane -> sink: the item's sinks are the contiguous slots [first, first+count)
+    const int s = lane < count ? first + lane : -1;
+    int lane_z = za;
+    for (int z = za; z < zb; ++z)
+      if (s >= uniform(off[pencil0 + z + 1])) lane_z = z + 1;
     const bool active = s >= 0;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) p = rel[s];
@@ -142,12 +151,12 @@ __global__ __launch_bounds__(256) void k_pair_forward(
             const float qz = p.z - (float)oz;
             if (kCount) npairs += end - beg;
             if (kAcc == kAccSingle) {
-              sum_sources(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
+              sum_sources<kU, kPipe>(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
-                sum_sources(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
+                sum_sources<kU, kPipe>(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
                 if (kAcc == kAccChunked) {
                   ax += tx; ay += ty; az += tz;
                 } else {
@@ -176,33 +185,51 @@ __global__ __launch_bounds__(256) void k_pair_forward(
   }
 }
 
-template <int kAcc, bool kCount>
+template <int kAcc, bool kCount, int kU, bool kPipe>
 static hipError_t launch_forward_t(const DevBox* boxes, const PlanWork& w, int64_t pencils,
                                    const int32_t* off, const float* rel, const int32_t* perm,
-                                   float* acc, int64_t* pair_count, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&k_pair_forward<kAcc, kCount>);
-  const int blocks = persistent_blocks(fn, 256);
-  hipLaunchKernelGGL((k_pair_forward<kAcc, kCount>), dim3(blocks), dim3(256), 0, s, boxes,
-                     w.items, w.queue, w.item_base + pencils, plan_head(w), off,
+                                   float* acc, int64_t* pair_count, int grid_mult, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_pair_forward<kAcc, kCount, kU, kPipe>);
+  const int blocks = persistent_blocks(fn, 256) * grid_mult;
+  hipLaunchKernelGGL((k_pair_forward<kAcc, kCount, kU, kPipe>), dim3(blocks), dim3(256), 0, s,
+                     boxes, w.items, w.queue, w.item_base + pencils, plan_head(w), off,
                      reinterpret_cast<const float4*>(rel), perm, acc,
                      reinterpret_cast<unsigned long long*>(pair_count));
   return hipGetLastError();
 }
 
-hipError_t launch_forward(AccMode mode, bool count_pairs, const DevBox* boxes, const PlanWork& w,
-                          int64_t pencils, const int32_t* off, const float* rel,
-                          const int32_t* perm, float* acc, int64_t* pair_count, hipStream_t s) {
+template <int kAcc, bool kCount>
+static hipError_t dispatch_variant(const KernelConfig& cfg, const DevBox* boxes, const PlanWork& w,
+                                   int64_t pencils, const int32_t* off, const float* rel,
+                                   const int32_t* perm, float* acc, int64_t* pc, hipStream_t s) {
+  const int g = cfg.grid_mult;
+  switch (cfg.unroll * 2 + (cfg.pipeline ? 1 : 0)) {
+    case 4: return launch_forward_t<kAcc, kCount, 2, false>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+    case 5: return launch_forward_t<kAcc, kCount, 2, true>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+    case 9: return launch_forward_t<kAcc, kCount, 4, true>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+    case 16: return launch_forward_t<kAcc, kCount, 8, false>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+    case 17: return launch_forward_t<kAcc, kCount, 8, true>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+    default: return launch_forward_t<kAcc, kCount, 4, false>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+  }
+}
+
+hipError_t launch_forward(AccMode mode, bool count_pairs, const KernelConfig& cfg,
+                          const DevBox* boxes, const PlanWork& w, int64_t pencils,
+                          const int32_t* off, const float* rel, const int32_t* perm, float* acc,
+                          int64_t* pair_count, hipStream_t s) {
   if (count_pairs) {
+    // The debug counter is a correctness tool: one fixed variant per mode.
+    const KernelConfig base = default_config(0);
     switch (mode) {
-      case kAccSingle: return launch_forward_t<kAccSingle, true>(boxes, w, pencils, off, rel, perm, acc, pair_count, s);
-      case kAccChunked: return launch_forward_t<kAccChunked, true>(boxes, w, pencils, off, rel, perm, acc, pair_count, s);
-      default: return launch_forward_t<kAccCompensated, true>(boxes, w, pencils, off, rel, perm, acc, pair_count, s);
+      case kAccSingle: return dispatch_variant<kAccSingle, true>(base, boxes, w, pencils, off, rel, perm, acc, pair_count, s);
+      case kAccChunked: return dispatch_variant<kAccChunked, true>(base, boxes, w, pencils, off, rel, perm, acc, pair_count, s);
+      default: return dispatch_variant<kAccCompensated, true>(base, boxes, w, pencils, off, rel, perm, acc, pair_count, s);
     }
   }
   switch (mode) {
-    case kAccSingle: return launch_forward_t<kAccSingle, false>(boxes, w, pencils, off, rel, perm, acc, nullptr, s);
-    case kAccChunked: return launch_forward_t<kAccChunked, false>(boxes, w, pencils, off, rel, perm, acc, nullptr, s);
-    default: return launch_forward_t<kAccCompensated, false>(boxes, w, pencils, off, rel, perm, acc, nullptr, s);
+    case kAccSingle: return dispatch_variant<kAccSingle, false>(cfg, boxes, w, pencils, off, rel, perm, acc, nullptr, s);
+    case kAccChunked: return dispatch_variant<kAccChunked, false>(cfg, boxes, w, pencils, off, rel, perm, acc, nullptr, s);
+    default: return dispatch_variant<kAccCompensated, false>(cfg, boxes, w, pencils, off, rel, perm, acc, nullptr, s);
   }
 }
 

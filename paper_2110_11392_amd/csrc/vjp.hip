@@ -62,16 +62,38 @@ struct AdjConst {
   float c0, c1, c2, ha, hb, eps;
 };
 
+template <int kU, bool kPipe>
 __device__ __forceinline__ void sum_adjoint(const float4* __restrict__ src, int beg, int end,
                                             float qx, float qy, float qz, float wx, float wy,
                                             float wz, const AdjConst& k, float& gx, float& gy,
                                             float& gz) {
   int j = beg;
-  for (; j + 2 <= end; j += 2) {
-    const float4 s0 = src[2 * j + 0], w0 = src[2 * j + 1];
-    const float4 s1 = src[2 * j + 2], w1 = src[2 * j + 3];
-    adjoint(s0, w0, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
-    adjoint(s1, w1, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+  if (kPipe && j + kU <= end) {
+    float4 cs[kU], cw[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) { cs[u] = src[2 * (j + u)]; cw[u] = src[2 * (j + u) + 1]; }
+    for (; j + 2 * kU <= end; j += kU) {
+      float4 ns[kU], nw[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) { ns[u] = src[2 * (j + kU + u)]; nw[u] = src[2 * (j + kU + u) + 1]; }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        adjoint(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) { cs[u] = ns[u]; cw[u] = nw[u]; }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      adjoint(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+    j += kU;
+  }
+  for (; j + kU <= end; j += kU) {
+    float4 cs[kU], cw[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) { cs[u] = src[2 * (j + u)]; cw[u] = src[2 * (j + u) + 1]; }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      adjoint(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
   }
   for (; j < end; ++j)
     adjoint(src[2 * j], src[2 * j + 1], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb,
@@ -90,7 +112,7 @@ __global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ r
   src[2 * s + 1] = make_float4(w[3 * i + 0], w[3 * i + 1], w[3 * i + 2], 0.0f);
 }
 
-template <int kAcc>
+template <int kAcc, int kU, bool kPipe>
 __global__ __launch_bounds__(256) void k_pair_vjp(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
     const int32_t* __restrict__ queue, const int32_t* __restrict__ n_items_ptr,
@@ -105,34 +127,25 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
     q = uni(__shfl(q, 0, 64));
     if (q >= n_items) break;
     const int4 it = items[uni(queue[q])];
-    const int b = uni(it.x);
+    const int b = uni(it.x & 0xffff), count = uni(it.x >> 16);
     const int cx = uni(it.y & 0xffff), cy = uni(it.y >> 16);
     const int za = uni(it.z & 0xffff), zb = uni(it.z >> 16);
-    const int tile = uni(it.w);
+    const int first = uni(it.w);
     const int K = uni(boxes[b].K), R = uni(boxes[b].R);
     const int cbase = uni(boxes[b].cell_base);
     AdjConst kc;
     kc.c0 = boxes[b].c0; kc.c1 = boxes[b].c1; kc.c2 = boxes[b].c2;
     kc.ha = boxes[b].ha; kc.hb = boxes[b].hb; kc.eps = boxes[b].eps;
+    // c1 and ha each meet another SGPR operand in an FMA; a VALU instruction
+    // reads at most one SGPR, so keep them in VGPRs for the whole item.
+    asm volatile("" : "+v"(kc.c1), "+v"(kc.ha));
     const int pencil0 = cbase + (cx * K + cy) * K;
 
-    int s = -1, lane_z = za;
-    if (tile >= 0) {
-      const int c = pencil0 + za;
-      const int beg = uni(off[c]) + tile * kTile, end = uni(off[c + 1]);
-      if (beg + lane < end) s = beg + lane;
-    } else {
-      int cum = 0;
-      for (int z = za; z <= zb; ++z) {
-        const int o0 = uni(off[pencil0 + z]), o1 = uni(off[pencil0 + z + 1]);
-        const int rem = (o1 - o0) & (kTile - 1);
-        if (lane >= cum && lane < cum + rem) {
-          s = o1 - rem + (lane - cum);
-          lane_z = z;
-        }
-        cum += rem;
-      }
-    }
+    // lane -> sink: the item's sinks are the contiguous slots [first, first+count)
+    const int s = lane < count ? first + lane : -1;
+    int lane_z = za;
+    for (int z = za; z < zb; ++z)
+      if (s >= uni(off[pencil0 + z + 1])) lane_z = z + 1;
     const bool active = s >= 0;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f), wk = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) {
@@ -156,12 +169,12 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
           if (active && oz >= -R && oz <= R) {
             const float qz = p.z - (float)oz;
             if (kAcc == kAccSingle) {
-              sum_adjoint(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx, gy, gz);
+              sum_adjoint<kU, kPipe>(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx, gy, gz);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
-                sum_adjoint(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx, ty, tz);
+                sum_adjoint<kU, kPipe>(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx, ty, tz);
                 if (kAcc == kAccChunked) {
                   gx += tx; gy += ty; gz += tz;
                 } else {
@@ -185,29 +198,43 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
   }
 }
 
-template <int kAcc>
+template <int kAcc, int kU, bool kPipe>
 static hipError_t launch_vjp_t(const DevBox* boxes, const PlanWork& w, int64_t pencils,
                                const int32_t* off, const float4* src, const int32_t* perm,
-                               float* grad, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&k_pair_vjp<kAcc>);
-  const int blocks = persistent_blocks(fn, 256);
-  hipLaunchKernelGGL((k_pair_vjp<kAcc>), dim3(blocks), dim3(256), 0, s, boxes, w.items, w.queue,
-                     w.item_base + pencils, plan_head(w), off, src, perm, grad);
+                               float* grad, int grid_mult, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_pair_vjp<kAcc, kU, kPipe>);
+  const int blocks = persistent_blocks(fn, 256) * grid_mult;
+  hipLaunchKernelGGL((k_pair_vjp<kAcc, kU, kPipe>), dim3(blocks), dim3(256), 0, s, boxes, w.items,
+                     w.queue, w.item_base + pencils, plan_head(w), off, src, perm, grad);
   return hipGetLastError();
 }
 
-hipError_t launch_vjp(AccMode mode, const DevBox* boxes, const PlanWork& w, int64_t pencils,
-                      const int32_t* off, const float* rel, const int32_t* perm, const float* wvec,
-                      float4* src_w, int64_t n_total, float* grad, hipStream_t s) {
+template <int kAcc>
+static hipError_t dispatch_vjp(const KernelConfig& cfg, const DevBox* boxes, const PlanWork& w,
+                               int64_t pencils, const int32_t* off, const float4* src,
+                               const int32_t* perm, float* grad, hipStream_t s) {
+  const int g = cfg.grid_mult;
+  switch (cfg.unroll * 2 + (cfg.pipeline ? 1 : 0)) {
+    case 5: return launch_vjp_t<kAcc, 2, true>(boxes, w, pencils, off, src, perm, grad, g, s);
+    case 8: return launch_vjp_t<kAcc, 4, false>(boxes, w, pencils, off, src, perm, grad, g, s);
+    case 9: return launch_vjp_t<kAcc, 4, true>(boxes, w, pencils, off, src, perm, grad, g, s);
+    default: return launch_vjp_t<kAcc, 2, false>(boxes, w, pencils, off, src, perm, grad, g, s);
+  }
+}
+
+hipError_t launch_vjp(AccMode mode, const KernelConfig& cfg, const DevBox* boxes,
+                      const PlanWork& w, int64_t pencils, const int32_t* off, const float* rel,
+                      const int32_t* perm, const float* wvec, float4* src_w, int64_t n_total,
+                      float* grad, hipStream_t s) {
   if (n_total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_src, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(rel), perm, wvec, n_total, src_w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (mode) {
-    case kAccSingle: return launch_vjp_t<kAccSingle>(boxes, w, pencils, off, src_w, perm, grad, s);
-    case kAccChunked: return launch_vjp_t<kAccChunked>(boxes, w, pencils, off, src_w, perm, grad, s);
-    default: return launch_vjp_t<kAccCompensated>(boxes, w, pencils, off, src_w, perm, grad, s);
+    case kAccSingle: return dispatch_vjp<kAccSingle>(cfg, boxes, w, pencils, off, src_w, perm, grad, s);
+    case kAccChunked: return dispatch_vjp<kAccChunked>(cfg, boxes, w, pencils, off, src_w, perm, grad, s);
+    default: return dispatch_vjp<kAccCompensated>(cfg, boxes, w, pencils, off, src_w, perm, grad, s);
   }
 }
 

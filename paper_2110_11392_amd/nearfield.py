@@ -155,6 +155,35 @@ class NearField:
         return grad
 
 
+    # -- tuning ------------------------------------------------------------------
+    def autotune(self, binned: Binned, accumulation: str = "compensated") -> dict:
+        """Time the candidate launch shapes on this input and keep the fastest
+        (synchronises; do not call while capturing a graph)."""
+        scratch = torch.empty((max(self.n_total, 1), 3), dtype=torch.float32, device=self.device)
+        fwd, adj = _lib.Tuning(), _lib.Tuning()
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_autotune(self._boxes, self.nboxes, ctypes.byref(cs),
+                                                _ptr(scratch), ACCUMULATION[accumulation],
+                                                _ptr(self.workspace), self.workspace_bytes,
+                                                _stream(), ctypes.byref(fwd), ctypes.byref(adj)),
+                   "abacus_nf_autotune")
+        return {"forward": fwd.asdict(), "adjoint": adj.asdict()}
+
+    def get_tuning(self, kernel: int, accumulation: str = "compensated") -> dict:
+        t = _lib.Tuning()
+        _lib.check(self._lib.abacus_nf_get_tuning(self._boxes, self.nboxes,
+                                                  ACCUMULATION[accumulation], kernel,
+                                                  ctypes.byref(t)), "abacus_nf_get_tuning")
+        return t.asdict()
+
+    def set_tuning(self, kernel: int, tuning: Optional[dict],
+                   accumulation: str = "compensated") -> None:
+        t = None if tuning is None else ctypes.byref(_lib.Tuning(**tuning))
+        _lib.check(self._lib.abacus_nf_set_tuning(self._boxes, self.nboxes,
+                                                  ACCUMULATION[accumulation], kernel, t),
+                   "abacus_nf_set_tuning")
+
+
 class _NearFieldFn(torch.autograd.Function):
     """acc = near-field accelerations of pos; backward is the hand-written adjoint
     kernel on the binning saved by forward (binning is piecewise constant in pos,

@@ -123,3 +123,47 @@ def test_timing_hooks_without_gpu():
     assert lib.abacus_nf_timing_read(0, ctypes.byref(ms), ctypes.byref(n)) == 0
     assert ms.value == 0.0 and n.value == 0
     assert lib.abacus_nf_timing_read(7, None, None) == _lib.EINVAL
+
+
+def test_tuning_registry_validation():
+    """Get/set of launch shapes: validation and round trip (host-only calls)."""
+    lib = _lib.load()
+    b = boxes((5000, 1.0, 16, 2, 1e-3))
+    t = _lib.Tuning()
+    assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert (t.unroll, t.pipeline, t.span, t.grid_mult) == (4, 0, 2, 1)
+    assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_ADJOINT, ctypes.byref(t)) == 0
+    assert (t.unroll, t.span) == (2, 2)
+    new = _lib.Tuning(8, 1, 3, 2)
+    assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(new)) == 0
+    assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert t.asdict() == {"unroll": 8, "pipeline": 1, "span": 3, "grid_mult": 2}
+    # other accumulation mode is a different key
+    assert lib.abacus_nf_get_tuning(b, 1, _lib.CHUNKED, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert t.unroll == 4
+    assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD, None) == 0
+    assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert t.unroll == 4
+    for bad in (_lib.Tuning(3, 0, 2, 1), _lib.Tuning(4, 2, 2, 1), _lib.Tuning(4, 0, 0, 1),
+                _lib.Tuning(4, 0, 4, 1), _lib.Tuning(4, 0, 2, 3)):
+        assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(bad)) == \
+            _lib.EINVAL
+    assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_ADJOINT,
+                                    ctypes.byref(_lib.Tuning(8, 0, 2, 1))) == _lib.EINVAL
+    assert lib.abacus_nf_set_tuning(b, 1, 0, 2, None) == _lib.EINVAL
+    assert lib.abacus_nf_get_tuning(b, 1, 0, 0, None) == _lib.EINVAL
+
+
+def test_autotune_validates_before_device_work():
+    lib = _lib.load()
+    b = boxes((100, 1.0, 8, 2, 1e-3))
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    fake = ctypes.c_void_p(0x1000)
+    nbytes = ctypes.c_size_t(0)
+    lib.abacus_nf_workspace_bytes(b, 1, ctypes.byref(nbytes))
+    assert lib.abacus_nf_autotune(b, 1, ctypes.byref(binned), None, 0, fake, nbytes, None, None,
+                                  None) == _lib.EINVAL
+    assert lib.abacus_nf_autotune(b, 1, ctypes.byref(binned), fake, _lib.COUNT_PAIRS, fake,
+                                  nbytes, None, None, None) == _lib.EINVAL
+    assert lib.abacus_nf_autotune(b, 1, ctypes.byref(binned), fake, 0, fake, 16, None, None,
+                                  None) == _lib.EWORKSPACE

@@ -78,6 +78,9 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out) {
     d.eps = (float)e;
     d.ha = (float)(12.0 / (e * e * e * e * e));
     d.hb = (float)(-15.0 / (e * e * e * e));
+    // Points of cells two apart on an axis are >= 1 cell apart; with eps below
+    // half a cell no rounding can bring such a pair inside eps.
+    d.far_newton = e < 0.5 ? 1 : 0;
     n_total += x.n;
     cells_total += cells;
     pencils_total += K * K;

@@ -52,6 +52,8 @@ struct DevBox {
   float c0, c1, c2;     // f(r) = c0 + c1 r + c2 r^2 for r < eps (cell units), Eq. 3
   float eps;            // eps_s / w
   float ha, hb;         // h(r) = f'(r)/r = ha + hb / r for r < eps (cell units)
+  int32_t far_newton;   // 1 if eps < 1/2 cell: cells >= 2 apart on an axis hold only r > eps pairs
+  int32_t pad_;
 };
 
 constexpr int kBoxChunk = 24;  // boxes per table-writing launch (kernel argument size)

@@ -25,7 +25,11 @@ namespace anf {
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// One interaction: t += f(|d|) d with d = s - q (cell units).
+// One interaction: t += f(|d|) d with d = s - q (cell units).  kNear: the pair
+// may lie inside the softening length, so f = min(spline(r), 1/r^3); otherwise
+// the source cell is so far from every sink that r > eps for all its pairs and
+// f = 1/r^3 -- exactly the value the minimum would select.
+template <bool kNear>
 __device__ __forceinline__ void interact(const float4 s, float qx, float qy, float qz, float c0,
                                          float c1, float c2, float& tx, float& ty, float& tz) {
   const float dx = s.x - qx;
@@ -33,10 +37,13 @@ __device__ __forceinline__ void interact(const float4 s, float qx, float qy, flo
   const float dz = s.z - qz;
   const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, kTinyR2)));
   const float rinv = rsq(r2);
-  const float r = r2 * rinv;
-  const float spline = __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0);
   const float rinv3 = (rinv * rinv) * rinv;
-  const float f = __builtin_fminf(spline, rinv3);
+  float f = rinv3;
+  if (kNear) {
+    const float r = r2 * rinv;
+    const float spline = __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0);
+    f = __builtin_fminf(spline, rinv3);
+  }
   tx = __builtin_fmaf(f, dx, tx);
   ty = __builtin_fmaf(f, dy, ty);
   tz = __builtin_fmaf(f, dz, tz);
@@ -62,7 +69,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Sum the sources [beg, end) into (tx, ty, tz), kU per step.  With kPipe the
 // next kU sources are requested before the current ones are used, so the
 // scalar-cache latency of one group overlaps the arithmetic of the previous.
-template <int kU, bool kPipe>
+template <int kU, bool kPipe, bool kNear>
 __device__ __forceinline__ void sum_sources(const float4* __restrict__ rel, int beg, int end,
                                             float qx, float qy, float qz, float c0, float c1,
                                             float c2, float& tx, float& ty, float& tz) {
@@ -76,12 +83,12 @@ __device__ __forceinline__ void sum_sources(const float4* __restrict__ rel, int 
 #pragma unroll
       for (int u = 0; u < kU; ++u) nxt[u] = rel[j + kU + u];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) interact(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+      for (int u = 0; u < kU; ++u) interact<kNear>(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
 #pragma unroll
       for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) interact(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+    for (int u = 0; u < kU; ++u) interact<kNear>(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
     j += kU;
   }
   for (; j + kU <= end; j += kU) {
@@ -89,9 +96,9 @@ __device__ __forceinline__ void sum_sources(const float4* __restrict__ rel, int 
 #pragma unroll
     for (int u = 0; u < kU; ++u) cur[u] = rel[j + u];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) interact(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+    for (int u = 0; u < kU; ++u) interact<kNear>(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
   }
-  for (; j < end; ++j) interact(rel[j], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+  for (; j < end; ++j) interact<kNear>(rel[j], qx, qy, qz, c0, c1, c2, tx, ty, tz);
 }
 
 template <int kAcc, bool kCount, int kU, bool kPipe>
@@ -122,6 +129,9 @@ __global__ __launch_bounds__(256) void k_pair_forward(
     float c1 = boxes[b].c1;
     asm volatile("" : "+v"(c1));
     const int pencil0 = cbase + (cx * K + cy) * K;
+    // Cells two or more apart on some axis are >= 1 cell width apart, so with
+    // eps < 1/2 cell every pair in them is Newtonian (f = 1/r^3).
+    const bool far_ok = uniform(boxes[b].far_newton) != 0;
 
     // ---- which sink this lane owns -------------------------------------
     // lane -> sink: the item's sinks are the contiguous slots [first, first+count)
@@ -142,21 +152,30 @@ __global__ __launch_bounds__(256) void k_pair_forward(
         const int sy = wrap1(cy + oy, K);
         const float qy = p.y - (float)oy;
         const int col = cbase + (sx * K + sy) * K;
+        const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
         for (int zu = za - R; zu <= zb + R; ++zu) {
           const int sz = wrap1(zu, K);
           const int beg = uniform(off[col + sz]), end = uniform(off[col + sz + 1]);
           if (beg == end) continue;
           const int oz = zu - lane_z;
+          // Wave-uniform: can any pair of this source cell fall inside eps?
+          const bool near = !far_ok || (col_near && zu >= za - 1 && zu <= zb + 1);
           if (active && oz >= -R && oz <= R) {
             const float qz = p.z - (float)oz;
             if (kCount) npairs += end - beg;
             if (kAcc == kAccSingle) {
-              sum_sources<kU, kPipe>(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
+              if (near)
+                sum_sources<kU, kPipe, true>(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
+              else
+                sum_sources<kU, kPipe, false>(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
-                sum_sources<kU, kPipe>(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
+                if (near)
+                  sum_sources<kU, kPipe, true>(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
+                else
+                  sum_sources<kU, kPipe, false>(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
                 if (kAcc == kAccChunked) {
                   ax += tx; ay += ty; az += tz;
                 } else {

@@ -17,6 +17,9 @@ namespace anf {
 
 __device__ __forceinline__ float rsq_v(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// kNear: the pair may lie inside eps (select between spline and Newton); else
+// every pair of the source cell has r > eps and the Newton branch is exact.
+template <bool kNear>
 __device__ __forceinline__ void adjoint(const float4 s, const float4 ws, float qx, float qy,
                                         float qz, float wx, float wy, float wz, float c0, float c1,
                                         float c2, float ha, float hb, float eps, float& gx,
@@ -26,12 +29,16 @@ __device__ __forceinline__ void adjoint(const float4 s, const float4 ws, float q
   const float dz = s.z - qz;
   const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, kTinyR2)));
   const float rinv = rsq_v(r2);
-  const float r = r2 * rinv;
   const float rinv2 = rinv * rinv;
   const float rinv3 = rinv2 * rinv;
-  const bool inner = r < eps;
-  const float f = inner ? __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0) : rinv3;
-  const float h = inner ? __builtin_fmaf(hb, rinv, ha) : (-3.0f * rinv2) * rinv3;
+  float f = rinv3;
+  float h = (-3.0f * rinv2) * rinv3;
+  if (kNear) {
+    const float r = r2 * rinv;
+    const bool inner = r < eps;
+    f = inner ? __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0) : rinv3;
+    h = inner ? __builtin_fmaf(hb, rinv, ha) : h;
+  }
   const float vx = ws.x - wx;
   const float vy = ws.y - wy;
   const float vz = ws.z - wz;
@@ -62,7 +69,7 @@ struct AdjConst {
   float c0, c1, c2, ha, hb, eps;
 };
 
-template <int kU, bool kPipe>
+template <int kU, bool kPipe, bool kNear>
 __device__ __forceinline__ void sum_adjoint(const float4* __restrict__ src, int beg, int end,
                                             float qx, float qy, float qz, float wx, float wy,
                                             float wz, const AdjConst& k, float& gx, float& gy,
@@ -78,13 +85,13 @@ __device__ __forceinline__ void sum_adjoint(const float4* __restrict__ src, int 
       for (int u = 0; u < kU; ++u) { ns[u] = src[2 * (j + kU + u)]; nw[u] = src[2 * (j + kU + u) + 1]; }
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        adjoint(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+        adjoint<kNear>(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
 #pragma unroll
       for (int u = 0; u < kU; ++u) { cs[u] = ns[u]; cw[u] = nw[u]; }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-      adjoint(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+      adjoint<kNear>(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
     j += kU;
   }
   for (; j + kU <= end; j += kU) {
@@ -93,10 +100,10 @@ __device__ __forceinline__ void sum_adjoint(const float4* __restrict__ src, int 
     for (int u = 0; u < kU; ++u) { cs[u] = src[2 * (j + u)]; cw[u] = src[2 * (j + u) + 1]; }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-      adjoint(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+      adjoint<kNear>(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
   }
   for (; j < end; ++j)
-    adjoint(src[2 * j], src[2 * j + 1], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb,
+    adjoint<kNear>(src[2 * j], src[2 * j + 1], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb,
             k.eps, gx, gy, gz);
 }
 
@@ -140,6 +147,7 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
     // reads at most one SGPR, so keep them in VGPRs for the whole item.
     asm volatile("" : "+v"(kc.c1), "+v"(kc.ha));
     const int pencil0 = cbase + (cx * K + cy) * K;
+    const bool far_ok = uni(boxes[b].far_newton) != 0;
 
     // lane -> sink: the item's sinks are the contiguous slots [first, first+count)
     const int s = lane < count ? first + lane : -1;
@@ -161,20 +169,32 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
         const int sy = wrap1_v(cy + oy, K);
         const float qy = p.y - (float)oy;
         const int col = cbase + (sx * K + sy) * K;
+        const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
         for (int zu = za - R; zu <= zb + R; ++zu) {
           const int sz = wrap1_v(zu, K);
           const int beg = uni(off[col + sz]), end = uni(off[col + sz + 1]);
           if (beg == end) continue;
           const int oz = zu - lane_z;
+          const bool near = !far_ok || (col_near && zu >= za - 1 && zu <= zb + 1);
           if (active && oz >= -R && oz <= R) {
             const float qz = p.z - (float)oz;
             if (kAcc == kAccSingle) {
-              sum_adjoint<kU, kPipe>(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx, gy, gz);
+              if (near)
+                sum_adjoint<kU, kPipe, true>(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx,
+                                             gy, gz);
+              else
+                sum_adjoint<kU, kPipe, false>(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx,
+                                              gy, gz);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
-                sum_adjoint<kU, kPipe>(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx, ty, tz);
+                if (near)
+                  sum_adjoint<kU, kPipe, true>(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx,
+                                               ty, tz);
+                else
+                  sum_adjoint<kU, kPipe, false>(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx,
+                                                ty, tz);
                 if (kAcc == kAccChunked) {
                   gx += tx; gy += ty; gz += tz;
                 } else {

@@ -53,6 +53,12 @@ def small_boxes():
                                       synth.uniform(1500, 11)).astype(np.float32),
                                      1.0, 8, 2, 1 / 2000)],
         "box_3p7_K11": [synth.Box(synth.uniform(4000, 12, 3.7), 3.7, 11, 2, 3.7 / 640)],
+        # softening just below / above half a cell: the Newton-only path for
+        # cells two apart is on / off
+        "soft_0p45_cell": [synth.Box(synth.clustered(3000, 10, 8, 16), 1.0, 8, 2,
+                                     0.45 / 8 / 2.16)],
+        "soft_0p60_cell": [synth.Box(synth.clustered(3000, 10, 8, 17), 1.0, 8, 2,
+                                     0.60 / 8 / 2.16)],
         "batch_ragged": [synth.Box(synth.clustered(2500, 6, 8, 13), 1.0, 8, 2, 1 / 500),
                          synth.Box(np.zeros((0, 3), np.float32), 1.0, 5, 2, 1 / 500),
                          synth.Box(synth.uniform(1, 14), 2.0, 5, 2, 1 / 500),

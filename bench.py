@@ -9,12 +9,22 @@ Prints ONE JSON line.  ``value`` is the pair interactions evaluated per second
 over the whole step (every ordered near-field pair is evaluated once by the
 forward kernel and once by the adjoint kernel), in G/s.  Per-kernel durations
 come from HIP events the library records around its kernels on the stream they
-run on.  The default workload is the clustered single box N = 128^3, K = 32.
+run on.
 
-    python bench.py [--steps K] [--warmup W] [--workload C2|C3|C5|C1]
+Workloads (``--workload``):
+  C2 (default)  clustered single box N = 128^3, K = 32.
+  C3            clustered single box N = 256^3, K = 64.
+  C5, C1        the small differentiation / uniform cases.
+  C4            64 uneven clustered boxes: the batched path (one persistent
+                launch per kernel for all boxes, autotuned, replayed from a HIP
+                graph; ``value`` is the graph replay) measured beside 64
+                sequential per-box calls with the built-in shapes.
+
+    python bench.py [--steps K] [--warmup W] [--workload C2|C3|C4|C5|C1]
                     [--accumulation compensated|chunked|single] [--no-cpu-baseline]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,20 +39,44 @@ sys.path.insert(0, ROOT)
 # two three-component updates).
 FLOP_FWD = 26.0
 FLOP_ADJ = 47.0
-# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed)
-# x 2.4 GHz.
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 x 2.4 GHz.
 PEAK_FP32_TFLOPS = 157.3
 
 WORKLOADS = {
     "C1": "uniform N=4096 K=8 R=2 eps_p=1/640",
     "C2": "clustered N=2097152 (2000 blobs) K=32 R=2 eps_p=1/5120",
     "C3": "clustered N=16777216 (20000 blobs) K=64 R=2 eps_p=1/10240",
+    "C4": "64 clustered boxes, N_b log-uniform in [32^3, 128^3], K_b=(N_b/64)^(1/3), R=2",
     "C5": "clustered N=262144 (256 blobs) K=16 R=2 eps_p=1/2560",
 }
+# HBM traffic of the dominant kernel from rocprofv3 counter runs, kept beside
+# the profiles; used only while the kernel source is unchanged.
+TRAFFIC_FILES = {"C2": "profiles/hbm_traffic_clustered_N2M_K32.json"}
+KERNEL_SOURCES = {"forward": "paper_2110_11392_amd/csrc/pairs.hip",
+                  "adjoint": "paper_2110_11392_amd/csrc/vjp.hip"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha(kernel):
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kernel]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_bytes(workload, kernel):
+    """HBM bytes per launch of `kernel`, or None if not measured for this source."""
+    path = TRAFFIC_FILES.get(workload)
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    with open(os.path.join(ROOT, path)) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("source_sha256") != source_sha(kernel):
+        return None
+    kib = k["fetch_kib"] * rec["copy_fetch_factor"] + k["write_kib"] * rec["copy_write_factor"]
+    return kib * 1024.0
 
 
 def exact_pairs(cell_offsets, boxes):
@@ -64,13 +98,15 @@ def exact_pairs(cell_offsets, boxes):
     return total
 
 
-def cpu_baseline(box, budget_s=12.0):
+def cpu_baseline(boxes, budget_s=12.0):
     """The FP64 oracle (single thread) on a bounded sample of sinks of the same
-    workload: forward forces plus the adjoint for those sinks."""
+    workload (for batches: of its largest box): forward forces plus the adjoint
+    for those sinks."""
     import numpy as np
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
     from paper_2110_11392_amd import synth
+    box = max(boxes, key=lambda b: b.n)
     w = synth.gaussian_weights(box.n, 4242)
     order = synth.sample_indices(box.n, min(box.n, 200000), 4243)
     rng = np.random.default_rng(4244)
@@ -87,8 +123,64 @@ def cpu_baseline(box, budget_s=12.0):
         sinks_done += s.size
     dt = time.perf_counter() - t0
     return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sinks_done} random sinks of the same workload, FP64 forces + adjoint, "
-                      f"{pairs} pair evaluations in {dt:.1f} s (single thread)"}
+            "sample": f"{sinks_done} random sinks of the same workload (N={box.n}), FP64 forces "
+                      f"+ adjoint, {pairs} pair evaluations in {dt:.1f} s (single thread)"}
+
+
+class Stepper:
+    """Preallocated buffers and one step of the path for a list of boxes."""
+
+    def __init__(self, anf, torch, boxes, accumulation, dev, pos=None, wvec=None):
+        import numpy as np
+        from paper_2110_11392_amd import synth
+        self.torch = torch
+        self.nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer)
+                                 for b in boxes], device=dev)
+        nf = self.nf
+        self.pos = pos if pos is not None else \
+            torch.from_numpy(np.concatenate([b.pos for b in boxes])).to(dev)
+        self.wvec = wvec if wvec is not None else \
+            torch.from_numpy(synth.gaussian_weights(nf.n_total, 4242)).to(dev)
+        self.binned = nf.alloc_binned()
+        self.acc = torch.empty((nf.n_total, 3), dtype=torch.float32, device=dev)
+        self.grad = torch.empty_like(self.acc)
+        self.mom = torch.empty((nf.nboxes, 4), dtype=torch.float64, device=dev)
+        self.accumulation = accumulation
+
+    def step(self):
+        nf = self.nf
+        nf.bin(self.pos, out=self.binned)
+        nf.forces(self.binned, self.accumulation, out=self.acc, momentum_out=self.mom)
+        nf.forces_vjp(self.binned, self.wvec, self.accumulation, out=self.grad)
+
+    def capture(self):
+        torch = self.torch
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.step()
+        graph.replay()
+        torch.cuda.synchronize()
+        return graph
+
+
+def timed(torch, fn, steps):
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(steps):
+        fn()
+        log(f"[bench] step {k + 1}/{steps} enqueued")
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
 
 
 def main():
@@ -103,7 +195,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing candidates")
     ap.add_argument("--no-graph", action="store_true",
-                    help="skip the extra measurement of the step replayed from a HIP graph")
+                    help="skip the measurement of the step replayed from a HIP graph")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -132,105 +224,89 @@ def main():
 
     log(f"[bench] generating {args.workload}")
     boxes = synth.config(args.workload)
-    box = boxes[0]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer) for b in boxes],
-                       device=dev)
-    pos = torch.from_numpy(np.concatenate([b.pos for b in boxes])).to(dev)
-    wvec = torch.from_numpy(synth.gaussian_weights(nf.n_total, 4242)).to(dev)
-    binned = nf.alloc_binned()
-    acc = torch.empty((nf.n_total, 3), dtype=torch.float32, device=dev)
-    grad = torch.empty_like(acc)
-    mom = torch.empty((nf.nboxes, 4), dtype=torch.float64, device=dev)
-
-    def step():
-        nf.bin(pos, out=binned)
-        nf.forces(binned, args.accumulation, out=acc, momentum_out=mom)
-        nf.forces_vjp(binned, wvec, args.accumulation, out=grad)
+    st = Stepper(anf, torch, boxes, args.accumulation, dev)
+    nf = st.nf
 
     log("[bench] warmup")
     for _ in range(args.warmup):
-        step()
+        st.step()
     torch.cuda.synchronize()
-    binned.check_status()
+    st.binned.check_status()
     tuning = {"forward": nf.get_tuning(0, args.accumulation),
               "adjoint": nf.get_tuning(1, args.accumulation)}
     if not args.no_autotune:
         log("[bench] autotune")
-        tuning = nf.autotune(binned, args.accumulation)
+        tuning = nf.autotune(st.binned, args.accumulation)
         log(f"[bench] tuned {tuning}")
-        step()
+        st.step()
         torch.cuda.synchronize()
-    pairs = exact_pairs(binned.cell_offsets.cpu().numpy(), boxes)
+    pairs = exact_pairs(st.binned.cell_offsets.cpu().numpy(), boxes)
     log(f"[bench] pairs per evaluation: {pairs}")
 
     anf.timing_reset()
     anf.timing_enable(True)
-    stream = torch.cuda.current_stream()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    for k in range(args.steps):
-        step()
-        log(f"[bench] step {k + 1}/{args.steps} enqueued")
-    t1.record(stream)
-    torch.cuda.synchronize()
+    ms_eager = timed(torch, st.step, args.steps)
     anf.timing_enable(False)
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
     kt = {name: anf.timing_read(k) for name, k in
           (("forward", 0), ("adjoint", 1), ("bin", 2), ("plan", 3))}
     avg = {name: (ms / n if n else float("nan")) for name, (ms, n) in kt.items()}
+
     graph_ms = None
     if not args.no_graph:
         log("[bench] graph capture")
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        graph.replay()
-        torch.cuda.synchronize()
-        g0 = torch.cuda.Event(enable_timing=True)
-        g1 = torch.cuda.Event(enable_timing=True)
-        g0.record(stream)
-        for _ in range(args.steps):
-            graph.replay()
-        g1.record(stream)
-        torch.cuda.synchronize()
-        graph_ms = g0.elapsed_time(g1) / args.steps
+        graph = st.capture()
+        graph_ms = timed(torch, graph.replay, args.steps)
         log(f"[bench] graph replay {graph_ms:.3f} ms/step")
-    m = mom.cpu().numpy()
-    resid = float(np.abs(m[:, :3]).max() / m[:, 3].max())
 
+    sequential_ms = None
+    if args.workload == "C4":
+        log("[bench] 64 sequential per-box calls, built-in shapes, no graph")
+        per_box = []
+        first = 0
+        for b in boxes:
+            per_box.append(Stepper(anf, torch, [b], args.accumulation, dev,
+                                   pos=st.pos[first:first + b.n],
+                                   wvec=st.wvec[first:first + b.n]))
+            first += b.n
+
+        def sequential():
+            for s in per_box:
+                s.step()
+        sequential()
+        torch.cuda.synchronize()
+        sequential_ms = timed(torch, sequential, args.steps)
+        log(f"[bench] sequential {sequential_ms:.3f} ms/step")
+
+    m = st.mom.cpu().numpy()
+    resid = float((np.abs(m[:, :3]).max(axis=1) / m[:, 3]).max())
     fwd_tflops = FLOP_FWD * pairs / (avg["forward"] * 1e-3) / 1e12
     adj_tflops = FLOP_ADJ * pairs / (avg["adjoint"] * 1e-3) / 1e12
     dominant = "adjoint" if avg["adjoint"] >= avg["forward"] else "forward"
     achieved = adj_tflops if dominant == "adjoint" else fwd_tflops
+    tbytes = traffic_bytes(args.workload, dominant)
+    ms_value = graph_ms if (args.workload == "C4" and graph_ms is not None) else ms_eager
     out = {
         "metric": "near-field pair interactions/s (G) + particle updates/s; adjoint/forward time",
-        "value": 2.0 * pairs / (ms_step * 1e-3) / 1e9,
+        "value": 2.0 * pairs / (ms_value * 1e-3) / 1e9,
         "unit": "Gpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": ms_value,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
-                   "n": nf.n_total, "pairs_per_evaluation": pairs,
+                   "n": nf.n_total, "boxes": nf.nboxes, "pairs_per_evaluation": pairs,
                    "accumulation": args.accumulation,
                    "step": "bin + forward(+FP64 momentum) + adjoint",
+                   "timed": "graph replay" if ms_value == graph_ms else "eager calls",
                    "tuning": tuning},
+        "ms_per_step_eager": ms_eager,
         "ms_per_step_graph_replay": graph_ms,
         "forward_gpairs_per_s": pairs / (avg["forward"] * 1e-3) / 1e9,
         "adjoint_gpairs_per_s": pairs / (avg["adjoint"] * 1e-3) / 1e9,
@@ -240,13 +316,18 @@ def main():
         "momentum_residual": resid,
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "flop_per_pair": FLOP_ADJ if dominant == "adjoint" else FLOP_FWD,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": tbytes,
+                     "algorithmic_flop_per_launch": (FLOP_ADJ if dominant == "adjoint"
+                                                     else FLOP_FWD) * pairs,
                      "forward_tflops": fwd_tflops, "adjoint_tflops": adj_tflops},
     }
+    if sequential_ms is not None:
+        out["sequential_per_box_ms_per_step"] = sequential_ms
+        out["batched_speedup_vs_sequential"] = sequential_ms / ms_value
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(box)
+        out["cpu_baseline"] = cpu_baseline(boxes)
     print(json.dumps(out), flush=True)
 
 

@@ -21,6 +21,12 @@
  *                  cotangent, binning frozen (derived from Eq. 3).
  *   oracle_fd      a central finite difference of the same loss (binning
  *                  frozen), used to pin oracle_vjp.
+ *   oracle_density the apodized top-hat density estimate over the same near
+ *                  field (Sec. 3.4.4).
+ *
+ * The force law is a parameter of oracle_forces, oracle_vjp and oracle_fd:
+ * ORACLE_LAW_SPLINE is Eq. 3 with eps_s = 2.16 eps_p; ORACLE_LAW_PLUMMER is
+ * Eq. 2, F = d / (r^2 + eps_p^2)^(3/2), with eps_p as given.
  *
  * Readings of the paper taken here (Eq. 3 gives F(r) with no sign, G or mass):
  *   - attractive force, d = x_j - x_i, G*m = 1 for every particle;
@@ -45,6 +51,9 @@
 /* The spline softening length is 2.16 times the Plummer-equivalent length
  * (Sec. 3.2, same minimum pairwise orbital time). */
 static const double SPLINE_OVER_PLUMMER = 2.16;
+
+#define ORACLE_LAW_SPLINE 0
+#define ORACLE_LAW_PLUMMER 1
 
 /* ------------------------------------------------------------------------- */
 /* Cell assignment (Sec. 2.2, Sec. 3.5.1).                                     */
@@ -173,6 +182,41 @@ static double spline_h(double r, double eps)
     return -3.0 / (r * r * r * r * r);
 }
 
+/* Eq. 2, Plummer softening: F(d) = f(r) d with f = (r^2 + eps^2)^(-3/2), and
+ * h = f'(r)/r = -3 (r^2 + eps^2)^(-5/2). */
+static double plummer_f(double r, double eps)
+{
+    double s = r * r + eps * eps;
+    return 1.0 / (s * sqrt(s));
+}
+
+static double plummer_h(double r, double eps)
+{
+    double s = r * r + eps * eps;
+    return -3.0 / (s * s * sqrt(s));
+}
+
+/* The softening law selected by `law`, with its own softening length: the
+ * spline's eps_s = 2.16 eps_p, or eps_p itself for Plummer. */
+typedef struct { int law; double eps; } law_t;
+
+static int make_law(int32_t law, double eps_p, law_t *out)
+{
+    if (law == ORACLE_LAW_SPLINE) { out->law = law; out->eps = SPLINE_OVER_PLUMMER * eps_p; return ORACLE_OK; }
+    if (law == ORACLE_LAW_PLUMMER) { out->law = law; out->eps = eps_p; return ORACLE_OK; }
+    return ORACLE_EINVAL;
+}
+
+static double law_f(const law_t *l, double r)
+{
+    return l->law == ORACLE_LAW_PLUMMER ? plummer_f(r, l->eps) : spline_f(r, l->eps);
+}
+
+static double law_h(const law_t *l, double r)
+{
+    return l->law == ORACLE_LAW_PLUMMER ? plummer_h(r, l->eps) : spline_h(r, l->eps);
+}
+
 /*
  * The image of source j seen from sink i: for each axis the integer shift m
  * that brings the unwrapped cell difference into [-R, R]; returns 0 if j is not
@@ -228,7 +272,7 @@ static int64_t visit_near_field(const grid_t *g, const float *pos, double L, int
     return npairs;
 }
 
-typedef struct { double eps; double a[3]; } force_ctx;
+typedef struct { law_t law; double a[3]; } force_ctx;
 
 static void force_pair(void *vctx, int64_t i, int64_t j, const double d[3])
 {
@@ -236,7 +280,7 @@ static void force_pair(void *vctx, int64_t i, int64_t j, const double d[3])
     force_ctx *ctx = (force_ctx *)vctx;
     double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     if (r == 0.0) return; /* coincident: F(0) = f(0) * 0 = 0 */
-    double f = spline_f(r, ctx->eps);
+    double f = law_f(&ctx->law, r);
     for (int a = 0; a < 3; ++a) ctx->a[a] += f * d[a];
 }
 
@@ -247,17 +291,17 @@ static void force_pair(void *vctx, int64_t i, int64_t j, const double d[3])
  * (sink, source) pairs summed.
  */
 int oracle_forces(int64_t n, const float *pos, double L, int32_t K, int32_t R, double eps_p,
-                  int64_t nsink, const int64_t *sinks, double *acc, int64_t *npairs)
+                  int32_t law, int64_t nsink, const int64_t *sinks, double *acc, int64_t *npairs)
 {
     int rc = check_box(L, K, R, eps_p);
     if (rc) return rc;
+    force_ctx ctx;
+    if ((rc = make_law(law, eps_p, &ctx.law))) return rc;
     if (n < 0 || nsink < 0 || (n > 0 && !pos) || (nsink > 0 && !acc)) return ORACLE_EINVAL;
     grid_t g;
     rc = grid_build(&g, n, pos, L, K, NULL);
     if (rc) return rc;
     int64_t total = 0;
-    force_ctx ctx;
-    ctx.eps = SPLINE_OVER_PLUMMER * eps_p;
     for (int64_t k = 0; k < nsink; ++k) {
         int64_t i = sinks ? sinks[k] : k;
         if (i < 0 || i >= n) { grid_free(&g); return ORACLE_EINVAL; }
@@ -270,7 +314,7 @@ int oracle_forces(int64_t n, const float *pos, double L, int32_t K, int32_t R, d
     return ORACLE_OK;
 }
 
-typedef struct { double eps; const float *w; double g[3]; } vjp_ctx;
+typedef struct { law_t law; const float *w; double g[3]; } vjp_ctx;
 
 static void vjp_pair(void *vctx, int64_t k, int64_t j, const double d[3])
 {
@@ -280,12 +324,12 @@ static void vjp_pair(void *vctx, int64_t k, int64_t j, const double d[3])
     double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     if (r == 0.0) {
         /* limit r -> 0: H = f(0) I, the d d^T term vanishes */
-        double f0 = spline_f(0.0, ctx->eps);
+        double f0 = law_f(&ctx->law, 0.0);
         for (int a = 0; a < 3; ++a) ctx->g[a] += f0 * v[a];
         return;
     }
-    double f = spline_f(r, ctx->eps);
-    double h = spline_h(r, ctx->eps);
+    double f = law_f(&ctx->law, r);
+    double h = law_h(&ctx->law, r);
     double dv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
     for (int a = 0; a < 3; ++a) ctx->g[a] += f * v[a] + h * dv * d[a];
 }
@@ -297,16 +341,16 @@ static void vjp_pair(void *vctx, int64_t k, int64_t j, const double d[3])
  * units (a is box units, so g has units of a / length).
  */
 int oracle_vjp(int64_t n, const float *pos, const float *w, double L, int32_t K, int32_t R,
-               double eps_p, int64_t nsink, const int64_t *sinks, double *g_out)
+               double eps_p, int32_t law, int64_t nsink, const int64_t *sinks, double *g_out)
 {
     int rc = check_box(L, K, R, eps_p);
     if (rc) return rc;
+    vjp_ctx ctx;
+    if ((rc = make_law(law, eps_p, &ctx.law))) return rc;
     if (n < 0 || nsink < 0 || (n > 0 && (!pos || !w)) || (nsink > 0 && !g_out)) return ORACLE_EINVAL;
     grid_t g;
     rc = grid_build(&g, n, pos, L, K, NULL);
     if (rc) return rc;
-    vjp_ctx ctx;
-    ctx.eps = SPLINE_OVER_PLUMMER * eps_p;
     ctx.w = w;
     for (int64_t q = 0; q < nsink; ++q) {
         int64_t k = sinks ? sinks[q] : q;
@@ -319,7 +363,7 @@ int oracle_vjp(int64_t n, const float *pos, const float *w, double L, int32_t K,
     return ORACLE_OK;
 }
 
-typedef struct { double eps; const float *w; int axis; double h; double sum; } fd_ctx;
+typedef struct { law_t law; const float *w; int axis; double h; double sum; } fd_ctx;
 
 static void fd_pair(void *vctx, int64_t k, int64_t j, const double d[3])
 {
@@ -329,8 +373,8 @@ static void fd_pair(void *vctx, int64_t k, int64_t j, const double d[3])
     dp[ctx->axis] += ctx->h;
     double rm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
     double rp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
-    double fm = rm == 0.0 ? 0.0 : spline_f(rm, ctx->eps);
-    double fp = rp == 0.0 ? 0.0 : spline_f(rp, ctx->eps);
+    double fm = rm == 0.0 ? 0.0 : law_f(&ctx->law, rm);
+    double fp = rp == 0.0 ? 0.0 : law_f(&ctx->law, rp);
     for (int a = 0; a < 3; ++a) {
         double wk_minus_wj = (double)ctx->w[3 * k + a] - (double)ctx->w[3 * j + a];
         ctx->sum += wk_minus_wj * (fm * dm[a] - fp * dp[a]);
@@ -345,20 +389,61 @@ static void fd_pair(void *vctx, int64_t k, int64_t j, const double d[3])
  * near-field relation is symmetric.
  */
 int oracle_fd(int64_t n, const float *pos, const float *w, double L, int32_t K, int32_t R,
-              double eps_p, int64_t k, int32_t axis, double h, double *out)
+              double eps_p, int32_t law, int64_t k, int32_t axis, double h, double *out)
 {
     int rc = check_box(L, K, R, eps_p);
     if (rc) return rc;
+    fd_ctx ctx;
+    if ((rc = make_law(law, eps_p, &ctx.law))) return rc;
     if (n <= 0 || !pos || !w || !out || k < 0 || k >= n || axis < 0 || axis > 2 || !(h > 0.0))
         return ORACLE_EINVAL;
     grid_t g;
     rc = grid_build(&g, n, pos, L, K, NULL);
     if (rc) return rc;
-    fd_ctx ctx;
-    ctx.eps = SPLINE_OVER_PLUMMER * eps_p;
     ctx.w = w; ctx.axis = axis; ctx.h = h; ctx.sum = 0.0;
     visit_near_field(&g, pos, L, R, k, fd_pair, &ctx);
     *out = ctx.sum / (2.0 * h);
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+typedef struct { double b2; double sum; } density_ctx;
+
+static void density_pair(void *vctx, int64_t i, int64_t j, const double d[3])
+{
+    (void)i; (void)j;
+    density_ctx *ctx = (density_ctx *)vctx;
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 < ctx->b2) ctx->sum += 1.0 - r2 / ctx->b2;
+}
+
+/*
+ * oracle_density: the apodized top-hat density estimate of Sec. 3.4.4 for the
+ * listed sinks (all if NULL): rho_i = sum over j with r_ij < b of (1 - r_ij^2/b^2),
+ * j running over the sink itself (r = 0, weight 1) and its near-field
+ * neighbours.  Readings: the self term is included (the paper's GPU sum runs
+ * over every particle of the sink's own cell, the sink included) and the
+ * weight is normalised by b^2 so that an isolated particle has rho = 1.
+ * Requires 0 < b <= R L/K, so that every particle within b is in the near field.
+ */
+int oracle_density(int64_t n, const float *pos, double L, int32_t K, int32_t R, double b,
+                   int64_t nsink, const int64_t *sinks, double *rho)
+{
+    if (!(L > 0.0) || !isfinite(L) || R < 0 || K < 2 * R + 1) return ORACLE_EINVAL;
+    if (!(b > 0.0) || !(b <= (double)R * L / (double)K)) return ORACLE_EINVAL;
+    if (n < 0 || nsink < 0 || (n > 0 && !pos) || (nsink > 0 && !rho)) return ORACLE_EINVAL;
+    grid_t g;
+    int rc = grid_build(&g, n, pos, L, K, NULL);
+    if (rc) return rc;
+    density_ctx ctx;
+    ctx.b2 = b * b;
+    for (int64_t k = 0; k < nsink; ++k) {
+        int64_t i = sinks ? sinks[k] : k;
+        if (i < 0 || i >= n) { grid_free(&g); return ORACLE_EINVAL; }
+        ctx.sum = 1.0; /* the sink itself */
+        visit_near_field(&g, pos, L, R, i, density_pair, &ctx);
+        rho[k] = ctx.sum;
+    }
     grid_free(&g);
     return ORACLE_OK;
 }
@@ -369,3 +454,6 @@ double oracle_spline_over_plummer(void) { return SPLINE_OVER_PLUMMER; }
 /* Eq. 3 for one separation, exported for the closed-form tests. */
 double oracle_pair_f(double r, double eps_s) { return spline_f(r, eps_s); }
 double oracle_pair_h(double r, double eps_s) { return spline_h(r, eps_s); }
+/* Eq. 2 for one separation. */
+double oracle_plummer_f(double r, double eps_p) { return plummer_f(r, eps_p); }
+double oracle_plummer_h(double r, double eps_p) { return plummer_h(r, eps_p); }

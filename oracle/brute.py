@@ -8,7 +8,9 @@ periodic cell offset of j from i is within R on every axis (Sec. 3.4.1, the
 below half the box, so the minimum image is the neighbouring-cell image.
 
 The force law is Eq. 3 with eps_s = 2.16 eps_p (Sec. 3.2), evaluated with
-``numpy.polynomial.polynomial.polyval``.  This module pins the oracle's pair
+``numpy.polynomial.polynomial.polyval``, or Eq. 2 (Plummer, eps_p as given)
+written as the gradient of the potential -(r^2 + eps_p^2)^(-1/2) with
+``numpy.power``.  This module pins the oracle's pair
 enumeration, image choice and summation; the force law itself is pinned by the
 closed-form tests (Newton's law outside eps_s, the C2 matching conditions that
 define the spline, and the Plummer small-r limit of Eq. 2).
@@ -26,7 +28,7 @@ def cells(pos: np.ndarray, box: float, cpd: int) -> np.ndarray:
 
 
 def forces(pos: np.ndarray, box: float, cpd: int, radius: int, eps_plummer: float,
-           sinks=None, chunk: int = 256):
+           sinks=None, chunk: int = 256, law: str = "spline"):
     """FP64 accelerations of ``sinks`` (all if None) and the ordered pair count."""
     x = pos.astype(np.float64)
     n = x.shape[0]
@@ -48,7 +50,12 @@ def forces(pos: np.ndarray, box: float, cpd: int, radius: int, eps_plummer: floa
         with np.errstate(divide="ignore", invalid="ignore"):
             newton = 1.0 / r ** 3
         soft = npoly.polyval(u, [10.0, -15.0, 6.0]) / eps ** 3
-        f = np.where(u < 1.0, soft, newton)
+        if law == "plummer":
+            f = np.power(r * r + eps_plummer ** 2, -1.5)
+        elif law == "spline":
+            f = np.where(u < 1.0, soft, newton)
+        else:
+            raise ValueError(law)
         f = np.where(near & (r > 0), f, 0.0)
         out[b:b + ii.size] = np.einsum("ij,ijk->ik", f, d)
         npairs += int(near.sum())

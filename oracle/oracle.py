@@ -42,10 +42,11 @@ def _load():
     i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     vp = ctypes.c_void_p
     lib.oracle_bin.argtypes = [i64, vp, dbl, i32, vp, vp, vp, vp]
-    lib.oracle_forces.argtypes = [i64, vp, dbl, i32, i32, dbl, i64, vp, vp, vp]
-    lib.oracle_vjp.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i64, vp, vp]
-    lib.oracle_fd.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i64, i32, dbl, vp]
-    for f in ("oracle_bin", "oracle_forces", "oracle_vjp", "oracle_fd"):
+    lib.oracle_forces.argtypes = [i64, vp, dbl, i32, i32, dbl, i32, i64, vp, vp, vp]
+    lib.oracle_vjp.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i32, i64, vp, vp]
+    lib.oracle_fd.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i32, i64, i32, dbl, vp]
+    lib.oracle_density.argtypes = [i64, vp, dbl, i32, i32, dbl, i64, vp, vp]
+    for f in ("oracle_bin", "oracle_forces", "oracle_vjp", "oracle_fd", "oracle_density"):
         getattr(lib, f).restype = ctypes.c_int
     lib.oracle_spline_over_plummer.restype = dbl
     lib.oracle_spline_over_plummer.argtypes = []
@@ -53,6 +54,10 @@ def _load():
     lib.oracle_pair_f.argtypes = [dbl, dbl]
     lib.oracle_pair_h.restype = dbl
     lib.oracle_pair_h.argtypes = [dbl, dbl]
+    lib.oracle_plummer_f.restype = dbl
+    lib.oracle_plummer_f.argtypes = [dbl, dbl]
+    lib.oracle_plummer_h.restype = dbl
+    lib.oracle_plummer_h.argtypes = [dbl, dbl]
     _lib = lib
     return lib
 
@@ -70,6 +75,16 @@ def _pos(pos) -> np.ndarray:
     if p.ndim != 2 or p.shape[1] != 3:
         raise ValueError("positions must be n x 3")
     return p
+
+
+# Force laws: Eq. 3 spline with eps_s = 2.16 eps_p, or Eq. 2 Plummer with eps_p.
+LAWS = {"spline": 0, "plummer": 1}
+
+
+def _law(law: str) -> int:
+    if law not in LAWS:
+        raise ValueError(f"unknown force law {law!r}")
+    return LAWS[law]
 
 
 def _check(rc: int, what: str):
@@ -91,6 +106,16 @@ def pair_h(r: float, eps_s: float) -> float:
     return _load().oracle_pair_h(float(r), float(eps_s))
 
 
+def plummer_f(r: float, eps_p: float) -> float:
+    """f(r) of Eq. 2 (F = f(r) d)."""
+    return _load().oracle_plummer_f(float(r), float(eps_p))
+
+
+def plummer_h(r: float, eps_p: float) -> float:
+    """h(r) = f'(r)/r of Eq. 2."""
+    return _load().oracle_plummer_h(float(r), float(eps_p))
+
+
 def bin(pos, box: float, cpd: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
     """Returns (cell[n], offsets[K^3+1], perm[n], rel[n,4]) as the oracle defines them."""
     p = _pos(pos)
@@ -105,7 +130,7 @@ def bin(pos, box: float, cpd: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray, 
 
 
 def forces(pos, box: float, cpd: int, radius: int, eps_plummer: float,
-           sinks: Optional[np.ndarray] = None) -> Tuple[np.ndarray, int]:
+           sinks: Optional[np.ndarray] = None, law: str = "spline") -> Tuple[np.ndarray, int]:
     """FP64 near-field accelerations (box units) of ``sinks`` (all if None) and the
     number of ordered pairs summed."""
     p = _pos(pos)
@@ -115,12 +140,13 @@ def forces(pos, box: float, cpd: int, radius: int, eps_plummer: float,
     acc = np.zeros((ns, 3), np.float64)
     npairs = ctypes.c_int64(0)
     _check(_load().oracle_forces(n, _ptr(p), float(box), int(cpd), int(radius), float(eps_plummer),
-                                 ns, _ptr(s), _ptr(acc), ctypes.byref(npairs)), "oracle_forces")
+                                 _law(law), ns, _ptr(s), _ptr(acc), ctypes.byref(npairs)),
+           "oracle_forces")
     return acc, int(npairs.value)
 
 
 def vjp(pos, w, box: float, cpd: int, radius: int, eps_plummer: float,
-        sinks: Optional[np.ndarray] = None) -> np.ndarray:
+        sinks: Optional[np.ndarray] = None, law: str = "spline") -> np.ndarray:
     """FP64 gradient of sum_i w_i . a_i with respect to the positions of ``sinks``."""
     p = _pos(pos)
     wv = np.ascontiguousarray(w, dtype=np.float32)
@@ -129,24 +155,38 @@ def vjp(pos, w, box: float, cpd: int, radius: int, eps_plummer: float,
     ns = n if s is None else s.shape[0]
     g = np.zeros((ns, 3), np.float64)
     _check(_load().oracle_vjp(n, _ptr(p), _ptr(wv), float(box), int(cpd), int(radius),
-                              float(eps_plummer), ns, _ptr(s), _ptr(g)), "oracle_vjp")
+                              float(eps_plummer), _law(law), ns, _ptr(s), _ptr(g)), "oracle_vjp")
     return g
 
 
 def fd(pos, w, box: float, cpd: int, radius: int, eps_plummer: float, k: int, axis: int,
-       h: float) -> float:
+       h: float, law: str = "spline") -> float:
     """Central difference D(h) of sum_i w_i . a_i along x_{k,axis}, binning frozen."""
     p = _pos(pos)
     wv = np.ascontiguousarray(w, dtype=np.float32)
     out = ctypes.c_double(0.0)
     _check(_load().oracle_fd(p.shape[0], _ptr(p), _ptr(wv), float(box), int(cpd), int(radius),
-                             float(eps_plummer), int(k), int(axis), float(h), ctypes.byref(out)),
+                             float(eps_plummer), _law(law), int(k), int(axis), float(h),
+                             ctypes.byref(out)),
            "oracle_fd")
     return float(out.value)
 
 
-def fd_richardson(pos, w, box, cpd, radius, eps_plummer, k, axis, h) -> float:
+def density(pos, box: float, cpd: int, radius: int, b: float,
+            sinks: Optional[np.ndarray] = None) -> np.ndarray:
+    """Apodized top-hat density sum_{r<b} (1 - r^2/b^2), self included (Sec. 3.4.4)."""
+    p = _pos(pos)
+    n = p.shape[0]
+    s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+    ns = n if s is None else s.shape[0]
+    rho = np.zeros(ns, np.float64)
+    _check(_load().oracle_density(n, _ptr(p), float(box), int(cpd), int(radius), float(b), ns,
+                                  _ptr(s), _ptr(rho)), "oracle_density")
+    return rho
+
+
+def fd_richardson(pos, w, box, cpd, radius, eps_plummer, k, axis, h, law="spline") -> float:
     """Richardson-extrapolated central difference (4 D(h/2) - D(h)) / 3."""
-    d1 = fd(pos, w, box, cpd, radius, eps_plummer, k, axis, h)
-    d2 = fd(pos, w, box, cpd, radius, eps_plummer, k, axis, h / 2)
+    d1 = fd(pos, w, box, cpd, radius, eps_plummer, k, axis, h, law)
+    d2 = fd(pos, w, box, cpd, radius, eps_plummer, k, axis, h / 2, law)
     return (4.0 * d2 - d1) / 3.0

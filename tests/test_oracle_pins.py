@@ -404,3 +404,120 @@ def test_vjp_sums_to_zero_and_is_symmetric():
     lhs = float(np.sum(v.astype(np.float64) * gw))
     rhs = float(np.sum(w.astype(np.float64) * gv))
     assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Top-hat density estimate (Sec. 3.4.4)
+# --------------------------------------------------------------------------
+
+def test_density_isolated_and_pairs():
+    K, R = 8, 2
+    w = 1.0 / K
+    b = 0.3 * w
+    # an isolated particle sees only itself
+    rho = oracle.density(np.array([[0.5, 0.5, 0.5]], np.float32), 1.0, K, R, b)
+    assert rho[0] == 1.0
+    # two particles at separation r < b: 1 + (1 - r^2/b^2) each; r >= b: 1
+    for r in (0.0, 0.1 * b, 0.77 * b, 0.999 * b, b, 1.5 * b):
+        x1 = np.array([0.5, 0.5, 0.5])
+        x2 = x1 + r * np.array([0.6, 0.0, 0.8])
+        pos = np.stack([x1, x2]).astype(np.float32)
+        d = pos[1].astype(np.float64) - pos[0].astype(np.float64)
+        rr = float(np.dot(d, d))
+        expect = 1.0 + (1.0 - rr / b ** 2 if rr < b ** 2 else 0.0)
+        rho = oracle.density(pos, 1.0, K, R, b)
+        assert rho == pytest.approx([expect, expect], rel=1e-14, abs=1e-15)
+
+
+def test_density_matches_numpy_brute_force():
+    n, K, R = 3000, 8, 2
+    pos = synth.clustered(n, 10, K, 91)
+    b = 0.5 / K
+    rho = oracle.density(pos, 1.0, K, R, b)
+    x = pos.astype(np.float64)
+    d = x[None, :, :] - x[:, None, :]
+    d -= np.rint(d)
+    r2 = np.sum(d * d, axis=2)
+    ref = np.where(r2 < b * b, 1.0 - r2 / (b * b), 0.0).sum(axis=1)  # includes self (r=0)
+    assert np.allclose(rho, ref, rtol=1e-12, atol=0)
+
+
+def test_density_rejects_radius_beyond_near_field():
+    pos = synth.uniform(100, 3)
+    with pytest.raises(oracle.OracleError):
+        oracle.density(pos, 1.0, 8, 2, 2.01 / 8)
+    with pytest.raises(oracle.OracleError):
+        oracle.density(pos, 1.0, 8, 2, 0.0)
+
+
+# --------------------------------------------------------------------------
+# Plummer softening (Eq. 2), the alternative force law
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("u", [0.0, 0.2, 1.0, 3.0, 40.0])
+def test_plummer_is_the_gradient_of_its_potential(u):
+    """Eq. 2 is the force of the potential -1/sqrt(r^2 + eps^2): F = -phi'(r) d/r,
+    so f(r) r equals the central difference of -phi; h = f'(r)/r likewise."""
+    eps = 0.01
+    r = u * eps
+    phi = lambda s: -1.0 / math.sqrt(s * s + eps * eps)
+    dr = 1e-4 * eps
+    if u > 0:
+        dphi = (phi(r + dr) - phi(r - dr)) / (2 * dr)
+        assert oracle.plummer_f(r, eps) * r == pytest.approx(dphi, rel=1e-7)
+        df = (oracle.plummer_f(r + dr, eps) - oracle.plummer_f(r - dr, eps)) / (2 * dr)
+        assert oracle.plummer_h(r, eps) == pytest.approx(df / r, rel=1e-6)
+    else:
+        # f(0) = phi''(0) = eps^-3, the harmonic core
+        d2phi = (phi(dr) - 2 * phi(0.0) + phi(-dr)) / dr ** 2
+        assert oracle.plummer_f(0.0, eps) == pytest.approx(d2phi, rel=1e-6)
+        assert oracle.plummer_f(0.0, eps) == pytest.approx(eps ** -3, rel=1e-15)
+
+
+def test_plummer_converges_quadratically_to_newton():
+    """Eq. 2 is not compact: f r^3 = 1 - (3/2) eps^2/r^2 + O(eps^4/r^4)."""
+    eps = 1e-3
+    for u in (30.0, 100.0, 300.0):
+        r = u * eps
+        deficit = 1.0 - oracle.plummer_f(r, eps) * r ** 3
+        assert deficit == pytest.approx(1.5 / u ** 2, rel=3.0 / u ** 2)
+
+
+@pytest.mark.parametrize("kind,n,cpd,seed", [("uniform", 1200, 7, 111), ("clustered", 1800, 8, 112)])
+def test_plummer_oracle_matches_brute_force(kind, n, cpd, seed):
+    pos = synth.uniform(n, seed) if kind == "uniform" else synth.clustered(n, 6, cpd, seed)
+    eps_p = 1.0 / (40 * n ** (1 / 3))
+    acc, npairs = oracle.forces(pos, 1.0, cpd, 2, eps_p, law="plummer")
+    ref, ref_pairs = brute.forces(pos, 1.0, cpd, 2, eps_p, law="plummer")
+    assert npairs == ref_pairs
+    err = np.linalg.norm(acc - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+    assert np.max(err) < 1e-10
+    spline, _ = oracle.forces(pos, 1.0, cpd, 2, eps_p)
+    assert not np.allclose(acc, spline, rtol=1e-6)   # the law argument is honoured
+
+
+def test_plummer_vjp_matches_richardson_fd_and_is_symmetric():
+    n, K, R = 1500, 8, 2
+    pos = synth.clustered(n, 8, K, 121)
+    w = synth.gaussian_weights(n, 122)
+    v = synth.gaussian_weights(n, 123)
+    eps_p = 1.0 / 400
+    rng = np.random.default_rng(124)
+    ks = rng.choice(n, size=16, replace=False)
+    axes = rng.integers(0, 3, size=16)
+    g = oracle.vjp(pos, w, 1.0, K, R, eps_p, sinks=ks, law="plummer")
+    for q, (k, a) in enumerate(zip(ks, axes)):
+        fd = oracle.fd_richardson(pos, w, 1.0, K, R, eps_p, int(k), int(a), 1e-3 * eps_p,
+                                  law="plummer")
+        assert fd == pytest.approx(g[q, a], rel=1e-6, abs=1e-9 * np.abs(g[q]).max())
+    gw = oracle.vjp(pos, w, 1.0, K, R, eps_p, law="plummer")
+    gv = oracle.vjp(pos, v, 1.0, K, R, eps_p, law="plummer")
+    assert np.all(np.abs(gw.sum(0)) <= 1e-12 * np.abs(gw).sum(0))
+    assert float(np.sum(v.astype(np.float64) * gw)) == pytest.approx(
+        float(np.sum(w.astype(np.float64) * gv)), rel=1e-11)
+
+
+def test_unknown_law_is_rejected():
+    pos = synth.uniform(50, 3)
+    with pytest.raises(ValueError):
+        oracle.forces(pos, 1.0, 8, 2, 1e-3, law="cubic")

@@ -23,6 +23,10 @@
  *                  frozen), used to pin oracle_vjp.
  *   oracle_density the apodized top-hat density estimate over the same near
  *                  field (Sec. 3.4.4).
+ *   oracle_multipoles  the cell multipoles of Eq. 4 in the complete basis of
+ *                  order p (Sec. 3.3.2), and their lossless reduction to
+ *                  (p+1)^2 values per cell using the harmonic (trace-free)
+ *                  property of the derivatives of 1/r.
  *
  * The force law is a parameter of oracle_forces, oracle_vjp and oracle_fd:
  * ORACLE_LAW_SPLINE is Eq. 3 with eps_s = 2.16 eps_p; ORACLE_LAW_PLUMMER is
@@ -444,6 +448,133 @@ int oracle_density(int64_t n, const float *pos, double L, int32_t K, int32_t R, 
         visit_near_field(&g, pos, L, R, i, density_pair, &ctx);
         rho[k] = ctx.sum;
     }
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cell multipoles, Eq. 4.                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* Number of complete-basis terms (a, b, c), a + b + c <= p: (p+3)(p+2)(p+1)/6. */
+int64_t oracle_multipole_terms(int32_t p, int32_t reduced)
+{
+    if (p < 0) return 0;
+    if (reduced) return (int64_t)(p + 1) * (p + 1);
+    return (int64_t)(p + 3) * (p + 2) * (p + 1) / 6;
+}
+
+/* Position of (a, b, c) in the complete basis, enumerated with a outermost and
+ * c innermost (a = 0..p, b = 0..p-a, c = 0..p-a-b). */
+static int64_t complete_index(int p, int a, int b, int c)
+{
+    int64_t k = 0;
+    for (int aa = 0; aa <= p; ++aa)
+        for (int bb = 0; bb <= p - aa; ++bb)
+            for (int cc = 0; cc <= p - aa - bb; ++cc) {
+                if (aa == a && bb == b && cc == c) return k;
+                ++k;
+            }
+    return -1;
+}
+
+static double factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return f;
+}
+
+static double binomial(int n, int k)
+{
+    return factorial(n) / (factorial(k) * factorial(n - k));
+}
+
+/*
+ * oracle_multipoles: for every cell of the K^3 grid, the complete multipoles of
+ * Eq. 4, M^{a,b,c} = sum_q x_q^a y_q^b z_q^c over the particles q of the cell,
+ * with (x_q, y_q, z_q) the particle's displacement from the cell centre in box
+ * units: its stored FP32 cell-relative offset (as oracle_bin makes it) times
+ * the cell width w = L/K.  The sum is formed in FP64 with the powers built by
+ * repeated multiplication, as the order loop of Eq. 4 reads.
+ *
+ * reduced != 0 instead returns (p+1)^2 values per cell: for c0 in {0, 1} and
+ * a + b + c0 <= p (same enumeration order, c restricted to {0, 1}),
+ *   R^{a,b,c0} = sum_{m>=0} sum_{i=0..m} (-1)^m C(m,i)
+ *                 a! b! c0! / ((a-2i)! (b-2m+2i)! (c0+2m)!) M^{a-2i, b-2m+2i, c0+2m}
+ * over the terms whose indices are non-negative.  This follows from the
+ * expansion phi(r) = sum_q 1/|r - x_q| = sum (-1)^n M^{abc}/(a!b!c!) D_{abc}(r),
+ * D_{abc} = d^a/dx^a d^b/dy^b d^c/dz^c (1/r): because 1/r is harmonic,
+ * D_{a,b,c+2} = -D_{a+2,b,c} - D_{a,b+2,c}, so every D with c >= 2 is a
+ * combination of those with c <= 1, and the reduced values give the same
+ * phi(r) = sum_{c0<=1} (-1)^n R^{a,b,c0}/(a!b!c0!) D_{a,b,c0}(r).
+ *
+ * out is K^3 x terms FP64, cell-major, cell id (x K + y) K + z.
+ */
+int oracle_multipoles(int64_t n, const float *pos, double L, int32_t K, int32_t p,
+                      int32_t reduced, double *out)
+{
+    if (n < 0 || (n > 0 && !pos) || !(L > 0.0) || !isfinite(L) || K < 1 || p < 0 || p > 16 || !out)
+        return ORACLE_EINVAL;
+    const int64_t ncell = (int64_t)K * K * K;
+    const int64_t cml = oracle_multipole_terms(p, 0);
+    double *M = (double *)calloc((size_t)(ncell * cml), sizeof(double));
+    float *rel = (float *)malloc(sizeof(float) * (size_t)(4 * (n > 0 ? n : 1)));
+    if (!M || !rel) { free(M); free(rel); return ORACLE_ENOMEM; }
+    grid_t g;
+    int rc = grid_build(&g, n, pos, L, K, rel);
+    if (rc) { free(M); free(rel); return rc; }
+    const double w = L / (double)K;
+    for (int64_t c = 0; c < ncell; ++c) {
+        double *Mc = M + c * cml;
+        for (int32_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+            const int64_t q = g.order[s];
+            const double X = (double)rel[4 * q + 0] * w;
+            const double Y = (double)rel[4 * q + 1] * w;
+            const double Z = (double)rel[4 * q + 2] * w;
+            int64_t k = 0;
+            double mx = 1.0;
+            for (int a = 0; a <= p; ++a) {
+                double mxy = mx;
+                for (int b = 0; b <= p - a; ++b) {
+                    double mxyz = mxy;
+                    for (int cc = 0; cc <= p - a - b; ++cc) {
+                        Mc[k++] += mxyz;
+                        mxyz *= Z;
+                    }
+                    mxy *= Y;
+                }
+                mx *= X;
+            }
+        }
+    }
+    if (!reduced) {
+        memcpy(out, M, sizeof(double) * (size_t)(ncell * cml));
+    } else {
+        const int64_t rml = oracle_multipole_terms(p, 1);
+        for (int64_t c = 0; c < ncell; ++c) {
+            const double *Mc = M + c * cml;
+            double *Rc = out + c * rml;
+            int64_t k = 0;
+            for (int a = 0; a <= p; ++a)
+                for (int b = 0; b <= p - a; ++b)
+                    for (int c0 = 0; c0 <= 1 && c0 <= p - a - b; ++c0) {
+                        double sum = 0.0;
+                        for (int m = 0; 2 * m <= a + b; ++m)
+                            for (int i = 0; i <= m; ++i) {
+                                const int sa = a - 2 * i, sb = b - 2 * (m - i), sc = c0 + 2 * m;
+                                if (sa < 0 || sb < 0) continue;
+                                const double coef = (m % 2 ? -1.0 : 1.0) * binomial(m, i) *
+                                                    factorial(a) * factorial(b) * factorial(c0) /
+                                                    (factorial(sa) * factorial(sb) * factorial(sc));
+                                sum += coef * Mc[complete_index(p, sa, sb, sc)];
+                            }
+                        Rc[k++] = sum;
+                    }
+        }
+    }
+    free(M);
+    free(rel);
     grid_free(&g);
     return ORACLE_OK;
 }

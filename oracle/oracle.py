@@ -46,7 +46,11 @@ def _load():
     lib.oracle_vjp.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i32, i64, vp, vp]
     lib.oracle_fd.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i32, i64, i32, dbl, vp]
     lib.oracle_density.argtypes = [i64, vp, dbl, i32, i32, dbl, i64, vp, vp]
-    for f in ("oracle_bin", "oracle_forces", "oracle_vjp", "oracle_fd", "oracle_density"):
+    lib.oracle_multipoles.argtypes = [i64, vp, dbl, i32, i32, i32, vp]
+    lib.oracle_multipole_terms.argtypes = [i32, i32]
+    lib.oracle_multipole_terms.restype = i64
+    for f in ("oracle_bin", "oracle_forces", "oracle_vjp", "oracle_fd", "oracle_density",
+              "oracle_multipoles"):
         getattr(lib, f).restype = ctypes.c_int
     lib.oracle_spline_over_plummer.restype = dbl
     lib.oracle_spline_over_plummer.argtypes = []
@@ -183,6 +187,20 @@ def density(pos, box: float, cpd: int, radius: int, b: float,
     _check(_load().oracle_density(n, _ptr(p), float(box), int(cpd), int(radius), float(b), ns,
                                   _ptr(s), _ptr(rho)), "oracle_density")
     return rho
+
+
+def multipole_terms(order: int, reduced: bool = False) -> int:
+    return int(_load().oracle_multipole_terms(int(order), 1 if reduced else 0))
+
+
+def multipoles(pos, box: float, cpd: int, order: int, reduced: bool = False) -> np.ndarray:
+    """Cell multipoles of Eq. 4 (K^3 x terms FP64, box units, about cell centres):
+    the complete basis of order p, or its (p+1)^2 reduction."""
+    p = _pos(pos)
+    out = np.zeros((cpd ** 3, multipole_terms(order, reduced)), np.float64)
+    _check(_load().oracle_multipoles(p.shape[0], _ptr(p), float(box), int(cpd), int(order),
+                                     1 if reduced else 0, _ptr(out)), "oracle_multipoles")
+    return out
 
 
 def fd_richardson(pos, w, box, cpd, radius, eps_plummer, k, axis, h, law="spline") -> float:

@@ -23,6 +23,9 @@
  *                  frozen), used to pin oracle_vjp.
  *   oracle_density the apodized top-hat density estimate over the same near
  *                  field (Sec. 3.4.4).
+ *   oracle_kick_drift  one leapfrog kick and drift (Sec. 2.1) with the per-cell
+ *                  rms velocity and maximum acceleration of the time-step
+ *                  criterion, Eq. 1; oracle_timestep evaluates Eq. 1.
  *   oracle_multipoles  the cell multipoles of Eq. 4 in the complete basis of
  *                  order p (Sec. 3.3.2), and their lossless reduction to
  *                  (p+1)^2 values per cell using the harmonic (trace-free)
@@ -577,6 +580,105 @@ int oracle_multipoles(int64_t n, const float *pos, double L, int32_t K, int32_t 
     free(rel);
     grid_free(&g);
     return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kick, drift and the time-step statistics (Sec. 2.1, Eq. 1).                 */
+/* ------------------------------------------------------------------------- */
+
+/* Periodic wrap of an FP64 coordinate into [0, L), rounded to FP32; a value
+ * that rounds up to L becomes 0. */
+static float wrap_coord(double t, double L)
+{
+    double q = floor(t / L);
+    double r = t - q * L;
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    float f = (float)r;
+    if (f >= (float)L) f = 0.0f;
+    return f;
+}
+
+/*
+ * oracle_kick_drift: for every particle (FP32 state, each update formed in FP64
+ * and rounded once to FP32, no fused multiply-add):
+ *   kick   v' = v + kick * a       (the velocity moves a full step, from the
+ *                                   half step before to the half step after)
+ *   drift  x' = wrap(x + drift * v')
+ * and, per cell of the grid that x (before the drift) falls in,
+ *   cell_stats[2c]   = v_rms = sqrt(sum |v'|^2 / n_c)  (mean not subtracted)
+ *   cell_stats[2c+1] = a_max = max |a|                 (0 for an empty cell)
+ * plus box_stats = {min over cells with n_c > 0 and a_max > 0 of v_rms/a_max
+ * (+inf if none), global v_rms = sqrt(sum |v'|^2 / N), global a_max, N}.
+ * |a| = sqrt(ax^2 + ay^2 + az^2) in FP64.  pos_out/vel_out may equal pos/vel.
+ */
+int oracle_kick_drift(int64_t n, const float *pos, const float *vel, const float *acc, double L,
+                      int32_t K, double kick, double drift, float *pos_out, float *vel_out,
+                      double *cell_stats, double *box_stats)
+{
+    if (n < 0 || (n > 0 && (!pos || !vel || !acc || !pos_out || !vel_out)) || !(L > 0.0) ||
+        !isfinite(L) || K < 1 || !isfinite(kick) || !isfinite(drift))
+        return ORACLE_EINVAL;
+    grid_t g;
+    int rc = grid_build(&g, n, pos, L, K, NULL);
+    if (rc) return rc;
+    const int64_t ncell = (int64_t)K * K * K;
+    double *sumsq = (double *)calloc((size_t)ncell, sizeof(double));
+    double *amax = (double *)calloc((size_t)ncell, sizeof(double));
+    if (!sumsq || !amax) { free(sumsq); free(amax); grid_free(&g); return ORACLE_ENOMEM; }
+    double total_sq = 0.0, global_amax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        float vn[3];
+        double v2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            vn[a] = (float)((double)vel[3 * i + a] + kick * (double)acc[3 * i + a]);
+            v2 += (double)vn[a] * (double)vn[a];
+        }
+        const double ax = acc[3 * i], ay = acc[3 * i + 1], az = acc[3 * i + 2];
+        const double am = sqrt(ax * ax + ay * ay + az * az);
+        const int32_t c = g.cell[i];
+        sumsq[c] += v2;
+        if (am > amax[c]) amax[c] = am;
+        total_sq += v2;
+        if (am > global_amax) global_amax = am;
+        for (int a = 0; a < 3; ++a) {
+            pos_out[3 * i + a] = wrap_coord((double)pos[3 * i + a] + drift * (double)vn[a], L);
+            vel_out[3 * i + a] = vn[a];
+        }
+    }
+    double min_ratio = INFINITY;
+    for (int64_t c = 0; c < ncell; ++c) {
+        const int32_t nc = g.start[c + 1] - g.start[c];
+        const double vr = nc > 0 ? sqrt(sumsq[c] / (double)nc) : 0.0;
+        if (cell_stats) {
+            cell_stats[2 * c] = vr;
+            cell_stats[2 * c + 1] = amax[c];
+        }
+        if (nc > 0 && amax[c] > 0.0 && vr / amax[c] < min_ratio) min_ratio = vr / amax[c];
+    }
+    if (box_stats) {
+        box_stats[0] = min_ratio;
+        box_stats[1] = n > 0 ? sqrt(total_sq / (double)n) : 0.0;
+        box_stats[2] = global_amax;
+        box_stats[3] = (double)n;
+    }
+    free(sumsq);
+    free(amax);
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+/* Eq. 1: the global step in scale factor,
+ *   da = min(eta_H a, eta_acc a H max(min_c [v_rms/a_max]_c, v_rms,global / a_max,global)),
+ * from box_stats as oracle_kick_drift returns them (a ratio with a_max = 0 is
+ * +inf and leaves the other terms to decide). */
+double oracle_timestep(const double *box_stats, double a, double H, double eta_acc, double eta_H)
+{
+    const double global = box_stats[2] > 0.0 ? box_stats[1] / box_stats[2] : INFINITY;
+    const double ratio = box_stats[0] > global ? box_stats[0] : global;
+    const double acc_step = eta_acc * a * H * ratio;
+    const double hubble_step = eta_H * a;
+    return acc_step < hubble_step ? acc_step : hubble_step;
 }
 
 /* The softening conversion constant, exported so tests can check it. */

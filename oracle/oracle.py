@@ -49,8 +49,11 @@ def _load():
     lib.oracle_multipoles.argtypes = [i64, vp, dbl, i32, i32, i32, vp]
     lib.oracle_multipole_terms.argtypes = [i32, i32]
     lib.oracle_multipole_terms.restype = i64
+    lib.oracle_kick_drift.argtypes = [i64, vp, vp, vp, dbl, i32, dbl, dbl, vp, vp, vp, vp]
+    lib.oracle_timestep.argtypes = [vp, dbl, dbl, dbl, dbl]
+    lib.oracle_timestep.restype = dbl
     for f in ("oracle_bin", "oracle_forces", "oracle_vjp", "oracle_fd", "oracle_density",
-              "oracle_multipoles"):
+              "oracle_multipoles", "oracle_kick_drift"):
         getattr(lib, f).restype = ctypes.c_int
     lib.oracle_spline_over_plummer.restype = dbl
     lib.oracle_spline_over_plummer.argtypes = []
@@ -201,6 +204,31 @@ def multipoles(pos, box: float, cpd: int, order: int, reduced: bool = False) -> 
     _check(_load().oracle_multipoles(p.shape[0], _ptr(p), float(box), int(cpd), int(order),
                                      1 if reduced else 0, _ptr(out)), "oracle_multipoles")
     return out
+
+
+def kick_drift(pos, vel, acc, box: float, cpd: int, kick: float, drift: float):
+    """One kick and drift with the Eq. 1 statistics: returns (pos', vel',
+    cell_stats (K^3 x 2: v_rms, a_max), box_stats (min_c v_rms/a_max, v_rms, a_max, N))."""
+    p = _pos(pos)
+    v = np.ascontiguousarray(vel, dtype=np.float32)
+    a = np.ascontiguousarray(acc, dtype=np.float32)
+    if v.shape != p.shape or a.shape != p.shape:
+        raise ValueError("pos, vel and acc must all be n x 3")
+    po = np.empty_like(p)
+    vo = np.empty_like(v)
+    cs = np.zeros((cpd ** 3, 2), np.float64)
+    bs = np.zeros(4, np.float64)
+    _check(_load().oracle_kick_drift(p.shape[0], _ptr(p), _ptr(v), _ptr(a), float(box), int(cpd),
+                                     float(kick), float(drift), _ptr(po), _ptr(vo), _ptr(cs),
+                                     _ptr(bs)), "oracle_kick_drift")
+    return po, vo, cs, bs
+
+
+def timestep(box_stats, a: float, H: float, eta_acc: float, eta_H: float) -> float:
+    """Eq. 1 from the statistics of kick_drift."""
+    bs = np.ascontiguousarray(box_stats, dtype=np.float64)
+    return float(_load().oracle_timestep(_ptr(bs), float(a), float(H), float(eta_acc),
+                                         float(eta_H)))
 
 
 def fd_richardson(pos, w, box, cpd, radius, eps_plummer, k, axis, h, law="spline") -> float:

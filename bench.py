@@ -169,6 +169,80 @@ class Stepper:
         return graph
 
 
+def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
+    """The widened rows, each timed by the library's own HIP events over `reps`
+    launches outside the main step: the density estimate fused into the
+    forward kernel, the Plummer law, the cell multipoles (p = 8, complete and
+    reduced) and the kick-drift step.  Returns per-row figures."""
+    import numpy as np
+    from paper_2110_11392_amd import synth
+    nf = st.nf
+    dev = st.pos.device
+    rows = {}
+
+    def kernel_ms(slot, fn):
+        fn()
+        torch.cuda.synchronize()
+        anf.timing_reset()
+        anf.timing_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        anf.timing_enable(False)
+        ms, n = anf.timing_read(slot)
+        return ms / n if n else float("nan")
+
+    fwd = kernel_ms(0, lambda: nf.forces(st.binned, accumulation, out=st.acc))
+    # density: b = 1/2 cell, every box
+    specs = [anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer, 0.5 * b.box / b.cpd)
+             for b in boxes]
+    nfd = anf.NearField(specs, device=dev)
+    nfd.set_tuning(0, nf.get_tuning(0, accumulation), accumulation)
+    rho = torch.empty(nf.n_total, dtype=torch.float32, device=dev)
+    dens = kernel_ms(0, lambda: nfd.forces(st.binned, accumulation, out=st.acc, density_out=rho))
+    rows["density"] = {"forward_ms": fwd, "forward_with_density_ms": dens,
+                       "overhead": dens / fwd - 1.0, "radius_cells": 0.5}
+    del nfd
+    # Plummer law (its own launch shapes: the built-in ones)
+    nfp = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer)
+                         for b in boxes], device=dev, law="plummer")
+    plum = kernel_ms(0, lambda: nfp.forces(st.binned, accumulation, out=st.acc))
+    rows["plummer"] = {"forward_ms": plum}
+    del nfp
+    # multipoles, p = 8
+    n, cells = nf.n_total, nf.cells_total
+    out_c = torch.empty((cells, 165), dtype=torch.float64, device=dev)
+    out_r = torch.empty((cells, 81), dtype=torch.float64, device=dev)
+    mp_c = kernel_ms(4, lambda: nf.multipoles(st.binned, 8, out=out_c))
+    mp_r = kernel_ms(4, lambda: nf.multipoles(st.binned, 8, reduced=True, out=out_r))
+    # algorithmic bytes: 16 B offsets per particle + offsets 4 B per cell read,
+    # 165 doubles per cell written (reduced: + complete rows read back, 81 written)
+    bytes_c = 16.0 * n + 4.0 * cells + 8.0 * 165 * cells
+    bytes_r = bytes_c + 8.0 * 165 * cells + 8.0 * 81 * cells
+    rows["multipoles_p8"] = {
+        "complete_ms": mp_c, "reduced_ms": mp_r,
+        "complete_gbps": bytes_c / (mp_c * 1e-3) / 1e9,
+        "reduced_gbps": bytes_r / (mp_r * 1e-3) / 1e9,
+        "hbm_peak_gbps": 8000.0,
+        "complete_frac_hbm": bytes_c / (mp_c * 1e-3) / 8e12,
+        "fp64_tflops_at_384_flop_per_particle": 384.0 * n / (mp_c * 1e-3) / 1e12,
+        "fp64_peak_tflops": 78.6}
+    del out_c, out_r
+    # kick-drift on copies of the state (the main step's inputs stay untouched)
+    pos = st.pos.clone()
+    vel = torch.from_numpy(synth.gaussian_weights(n, 77) * np.float32(0.05)).to(dev)
+    nf.forces(st.binned, accumulation, out=st.acc)
+    kd = kernel_ms(5, lambda: nf.kick_drift(st.binned, pos, vel, st.acc, 1e-6, 1e-6,
+                                            cell_stats=True))
+    # algorithmic bytes: pos, vel read and written, acc read (12 B each), perm
+    # 4 B per particle; offsets 4 B and statistics 16 B per cell
+    bytes_kd = (12.0 * 5 + 4.0) * n + 20.0 * cells
+    rows["kick_drift"] = {"ms": kd, "gbps": bytes_kd / (kd * 1e-3) / 1e9,
+                          "frac_hbm": bytes_kd / (kd * 1e-3) / 8e12,
+                          "note": "particles in the workload's original (not cell) order"}
+    return rows
+
+
 def timed(torch, fn, steps):
     stream = torch.cuda.current_stream()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -196,6 +270,8 @@ def main():
                     help="keep the built-in launch shapes instead of timing candidates")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the measurement of the step replayed from a HIP graph")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the density / Plummer / multipole / kick-drift figures")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -322,6 +398,9 @@ def main():
                                                      else FLOP_FWD) * pairs,
                      "forward_tflops": fwd_tflops, "adjoint_tflops": adj_tflops},
     }
+    if not args.no_rows:
+        log("[bench] widened rows: density, Plummer, multipoles, kick-drift")
+        out["rows"] = measure_rows(anf, torch, st, boxes, args.accumulation)
     if sequential_ms is not None:
         out["sequential_per_box_ms_per_step"] = sequential_ms
         out["batched_speedup_vs_sequential"] = sequential_ms / ms_value

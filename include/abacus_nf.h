@@ -66,19 +66,32 @@ extern "C" {
 /* Debug: count every evaluated (sink, source) pair, self excluded, into the
  * int64 at `pair_count` (abacus_nf_forces only).  Costs one atomic per work item. */
 #define ABACUS_NF_COUNT_PAIRS  0x10u
+/* Force law: Plummer softening of Eq. 2, F = d / (r^2 + eps_p^2)^(3/2), with the
+ * box's eps_plummer used as given, in place of the default spline of Eq. 3.
+ * Accepted by abacus_nf_forces, abacus_nf_forces_vjp and the tuning calls (the
+ * two laws keep separate launch shapes).  Every pair then takes the same plain
+ * branch; the validation of eps_plummer is unchanged. */
+#define ABACUS_NF_PLUMMER      0x20u
+/* abacus_nf_multipoles: return the (p+1)^2 reduced basis instead of the
+ * complete one. */
+#define ABACUS_NF_REDUCED      0x40u
 
 /* ---- data types --------------------------------------------------------- */
 
 /* One periodic box (Sec. 2.2 grid; Sec. 3.4.1 near-field radius; Sec. 3.2
- * softening).  Requirements: n >= 0; box > 0 and finite; radius >= 0;
- * cpd >= 2*radius + 1 (so the (2R+1)^3 stencil never wraps onto itself);
- * eps_plummer > 0 and finite with 1e-6 <= 2.16*eps_plummer*cpd/box <= 1e6. */
+ * softening; Sec. 3.4.4 density estimate).  Requirements: n >= 0; box > 0 and
+ * finite; radius >= 0; cpd >= 2*radius + 1 (so the (2R+1)^3 stencil never wraps
+ * onto itself); eps_plummer > 0 and finite with
+ * 1e-6 <= 2.16*eps_plummer*cpd/box <= 1e6; density_radius is 0 (no density
+ * estimate) or finite with 0 < density_radius*cpd/box <= radius and
+ * (density_radius*cpd/box)^2 >= 1e-30. */
 typedef struct {
     int64_t n;             /* number of particles in this box */
     double  box;           /* side L of the periodic cube */
     int32_t cpd;           /* cells per dimension K */
     int32_t radius;        /* near-field radius R in cells (the paper uses 2) */
     double  eps_plummer;   /* Plummer-equivalent softening; eps_s = 2.16 eps_p */
+    double  density_radius;/* top-hat radius b of the density estimate (box units), or 0 */
 } abacus_nf_box;
 
 /* Binned particles: the output of abacus_nf_bin, input of the force calls.
@@ -127,6 +140,13 @@ int abacus_nf_bin(const abacus_nf_box *boxes, int nboxes, const float *pos,
  * FP32 on cell-relative coordinates; the accumulation follows `flags`.
  *   b          binned arrays from abacus_nf_bin for the same boxes.
  *   acc        n_total x 3 FP32 output in ORIGINAL particle order, box units.
+ *   density    NULL, or n_total FP32 outputs in original order: the apodized
+ *              top-hat estimate of Sec. 3.4.4, rho_i = sum over the same
+ *              near-field points j (i itself included) with r_ij < b of
+ *              1 - r_ij^2/b^2, b = density_radius, accumulated as b^2 - r^2 in
+ *              cell units in the same pass as the forces (plain FP32 sums per
+ *              x offset, whatever the accumulation flag) and divided by b^2.
+ *              EINVAL if a box has density_radius 0 or with COUNT_PAIRS.
  *   momentum   NULL, or 4*nboxes FP64 outputs: per box (sum a_x, sum a_y,
  *              sum a_z, sum |a|), reduced in FP64 in a fixed order.  Pair
  *              antisymmetry makes the first three vanish up to rounding.
@@ -134,8 +154,8 @@ int abacus_nf_bin(const abacus_nf_box *boxes, int nboxes, const float *pos,
  *              when ABACUS_NF_COUNT_PAIRS is set.
  */
 int abacus_nf_forces(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
-                     float *acc, double *momentum, int64_t *pair_count, uint32_t flags,
-                     void *ws, size_t ws_bytes, void *stream);
+                     float *acc, float *density, double *momentum, int64_t *pair_count,
+                     uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * abacus_nf_forces_vjp -- vector-Jacobian product of the accelerations.
@@ -164,6 +184,8 @@ typedef struct {
     int32_t pipeline;   /* 1: request the next step's sources before using the current ones */
     int32_t span;       /* most cells one 64-sink work item spans along its pencil: 1, 2 or 3 */
     int32_t grid_mult;  /* persistent workgroups per resident slot: 1 or 2 */
+    int32_t split;      /* 1: split the cheapest work items at the end of the queue into one
+                           task per x offset (shorter tail; same results); 0: never */
 } abacus_nf_tuning;
 
 #define ABACUS_NF_KERNEL_FORWARD 0
@@ -174,7 +196,7 @@ typedef struct {
  * kernels on this binned input and keep the fastest for this problem shape
  * (box list, accumulation flags, device) in a process-wide table that later
  * abacus_nf_forces / abacus_nf_forces_vjp calls use.  The search is a
- * coordinate descent (span, then unroll/pipeline, then grid) with two timed
+ * coordinate descent (span, then unroll/pipeline, then grid, then split) with two timed
  * runs per candidate.  `scratch` is n_total x 3 FP32 device memory whose
  * contents are overwritten.  Unlike the other entry points this call
  * SYNCHRONISES `stream`; do not call it while capturing a graph.  If the
@@ -193,11 +215,94 @@ int abacus_nf_get_tuning(const abacus_nf_box *boxes, int nboxes, uint32_t flags,
 int abacus_nf_set_tuning(const abacus_nf_box *boxes, int nboxes, uint32_t flags, int kernel,
                          const abacus_nf_tuning *t);
 
+/* ---- cell multipoles (Eq. 4, Sec. 3.3.2) --------------------------------- */
+
+/* Terms per cell for multipole order p (0 <= p <= 8): (p+3)(p+2)(p+1)/6 in the
+ * complete basis, (p+1)^2 with ABACUS_NF_REDUCED.  EINVAL for another order or
+ * flag, or a NULL result pointer. */
+int abacus_nf_multipole_terms(int order, uint32_t flags, int64_t *terms);
+
+/* Workspace bytes of abacus_nf_multipoles for this box list, order and flags
+ * (a separate, usually smaller, size from abacus_nf_workspace_bytes; the
+ * reduced basis also keeps the complete rows there: 8 B x cells x terms). */
+int abacus_nf_multipoles_workspace_bytes(const abacus_nf_box *boxes, int nboxes, int order,
+                                         uint32_t flags, size_t *bytes);
+
+/*
+ * abacus_nf_multipoles -- the cell multipoles of every cell of every box.
+ * Complete basis (Eq. 4): M^{a,b,c} = sum over the particles q of the cell of
+ * x_q^a y_q^b z_q^c, (x, y, z) the particle's displacement from the cell centre
+ * in box units -- its stored FP32 cell-relative offset (b->rel) times w = L/K --
+ * for a + b + c <= order, enumerated with a outermost and c innermost
+ * (a = 0..p, b = 0..p-a, c = 0..p-a-b).  Sums are formed in FP64.
+ * With ABACUS_NF_REDUCED, (p+1)^2 values per cell: for c0 in {0, 1} and
+ * a + b + c0 <= p (same enumeration, c restricted to {0, 1}),
+ *   R^{a,b,c0} = sum_{m>=0} sum_{i=0..m} (-1)^m C(m,i) a! b! c0! /
+ *                ((a-2i)! (b-2m+2i)! (c0+2m)!) M^{a-2i, b-2m+2i, c0+2m}
+ * (terms with a negative index omitted): the far-field expansion
+ * sum (-1)^n M^{abc}/(a!b!c!) d^{abc}(1/r) keeps its value when the complete
+ * values are replaced by these, because 1/r is harmonic (the trace-free
+ * property the paper uses to store (p+1)^2 values).
+ *   b      binned arrays from abacus_nf_bin for the same boxes.
+ *   out    cells_total x terms FP64, cell-major in global cell order (box by
+ *          box, x slowest, z fastest); every cell is written, empty ones 0.
+ * Errors: EINVAL for a bad box, order outside [0, 8], an unknown flag or a
+ * NULL pointer; EWORKSPACE if ws is NULL, not 256-byte aligned or smaller
+ * than abacus_nf_multipoles_workspace_bytes.  Results are run-to-run
+ * deterministic.
+ */
+int abacus_nf_multipoles(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                         int order, uint32_t flags, double *out, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ---- kick, drift and the time step (Sec. 2.1, Eq. 1) --------------------- */
+
+/* Workspace bytes of abacus_nf_kick_drift (8 B x 2 per cell plus a little). */
+int abacus_nf_kick_drift_workspace_bytes(const abacus_nf_box *boxes, int nboxes,
+                                         size_t *bytes);
+
+/*
+ * abacus_nf_kick_drift -- one leapfrog kick and drift, in place, with the
+ * statistics of the time-step criterion.  For every particle i (FP32 state,
+ * each update formed in FP64 with a separate multiply and add and rounded once
+ * to FP32; same arithmetic as a plain C program compiled without contraction):
+ *   vel_i <- vel_i + kick[box] * acc_i          (a full step between half steps)
+ *   pos_i <- wrap(pos_i + drift[box] * vel_i)   (with the kicked velocity)
+ * wrap(t) = t - L floor(t / L) in FP64, brought into [0, L), rounded to FP32,
+ * and a value that rounds up to L set to 0.
+ *   b          binned arrays of the same positions (before this call): the
+ *              cells of the statistics are the cells of the binning.
+ *   kick, drift  host arrays of nboxes finite factors (the cosmology's
+ *              integrals over the step are the caller's).
+ *   pos, vel   n_total x 3 FP32, original order, updated in place.
+ *   acc        n_total x 3 FP32, original order (e.g. from abacus_nf_forces).
+ *   cell_stats NULL, or cells_total x 2 FP64: per cell v_rms = sqrt(sum |v|^2 / n)
+ *              over the kicked velocities (mean not subtracted, as the paper
+ *              does) and a_max = max |a|; 0 for an empty cell.
+ *   box_stats  NULL, or nboxes x 4 FP64: min over cells with n > 0 and
+ *              a_max > 0 of v_rms/a_max (+inf if none), the box's global
+ *              v_rms, global a_max and N -- the inputs of abacus_nf_timestep.
+ * Results are run-to-run deterministic.  Errors: EINVAL for a bad box, a NULL
+ * or non-finite factor, or NULL state arrays; EWORKSPACE as elsewhere.
+ */
+int abacus_nf_kick_drift(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                         const double *kick, const double *drift, float *pos, float *vel,
+                         const float *acc, double *cell_stats, double *box_stats, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* Eq. 1 for one box (host only):
+ *   da = min(eta_H a, eta_acc a H max(min_c [v_rms/a_max]_c, v_rms/a_max global))
+ * from the four box_stats values of abacus_nf_kick_drift; a global a_max of 0
+ * counts as an infinite ratio.  NaN if box_stats is NULL. */
+double abacus_nf_timestep(const double *box_stats, double a, double H, double eta_acc,
+                          double eta_H);
+
 /* ---- measurement hooks (not needed for computing) ------------------------ */
 /* When enabled, the library records HIP events around its pair kernels on the
  * caller's stream; abacus_nf_timing_read returns the summed milliseconds and
  * launch count per kernel (0 = forward pair kernel, 1 = adjoint pair kernel,
- * 2 = binning, 3 = work plan) since the last reset, synchronising on the events.
+ * 2 = binning, 3 = work plan, 4 = multipoles, 5 = kick-drift) since the last
+ * reset, synchronising on the events; EINVAL for another id.
  * Do not enable while capturing a graph. */
 int abacus_nf_timing_enable(int enable);
 int abacus_nf_timing_read(int kernel, double *ms, int64_t *launches);

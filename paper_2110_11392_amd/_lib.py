@@ -23,21 +23,27 @@ SINGLE_ACC = 0x1
 CHUNKED = 0x2
 COMPENSATED = 0x4
 COUNT_PAIRS = 0x10
+PLUMMER = 0x20
+REDUCED = 0x40
 
 TIMER_FORWARD = 0
 TIMER_ADJOINT = 1
 TIMER_BIN = 2
 TIMER_PLAN = 3
+TIMER_MULTIPOLES = 4
+TIMER_KICK_DRIFT = 5
 
 
 class Box(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("box", ctypes.c_double), ("cpd", ctypes.c_int32),
-                ("radius", ctypes.c_int32), ("eps_plummer", ctypes.c_double)]
+                ("radius", ctypes.c_int32), ("eps_plummer", ctypes.c_double),
+                ("density_radius", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("unroll", ctypes.c_int32), ("pipeline", ctypes.c_int32),
-                ("span", ctypes.c_int32), ("grid_mult", ctypes.c_int32)]
+                ("span", ctypes.c_int32), ("grid_mult", ctypes.c_int32),
+                ("split", ctypes.c_int32)]
 
     def asdict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -55,7 +61,9 @@ class Binned(ctypes.Structure):
 EXPORTS = ("abacus_nf_layout", "abacus_nf_workspace_bytes", "abacus_nf_bin", "abacus_nf_forces",
            "abacus_nf_forces_vjp", "abacus_nf_strerror", "abacus_nf_autotune",
            "abacus_nf_get_tuning", "abacus_nf_set_tuning", "abacus_nf_timing_enable",
-           "abacus_nf_timing_read", "abacus_nf_timing_reset")
+           "abacus_nf_timing_read", "abacus_nf_timing_reset", "abacus_nf_multipole_terms",
+           "abacus_nf_multipoles_workspace_bytes", "abacus_nf_multipoles",
+           "abacus_nf_kick_drift_workspace_bytes", "abacus_nf_kick_drift", "abacus_nf_timestep")
 
 _lib = None
 
@@ -82,7 +90,7 @@ def load() -> ctypes.CDLL:
     lib.abacus_nf_layout.argtypes = [BoxP, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.abacus_nf_workspace_bytes.argtypes = [BoxP, ctypes.c_int, ctypes.POINTER(sz)]
     lib.abacus_nf_bin.argtypes = [BoxP, ctypes.c_int, vp, BinnedP, vp, sz, vp]
-    lib.abacus_nf_forces.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, u32, vp, sz, vp]
+    lib.abacus_nf_forces.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, vp, u32, vp, sz, vp]
     lib.abacus_nf_forces_vjp.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, u32, vp, sz, vp]
     TuneP = ctypes.POINTER(Tuning)
     lib.abacus_nf_autotune.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp, TuneP,
@@ -95,9 +103,20 @@ def load() -> ctypes.CDLL:
     lib.abacus_nf_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(i64)]
     lib.abacus_nf_timing_reset.argtypes = []
+    lib.abacus_nf_multipole_terms.argtypes = [ctypes.c_int, u32, ctypes.POINTER(i64)]
+    lib.abacus_nf_multipoles_workspace_bytes.argtypes = [BoxP, ctypes.c_int, ctypes.c_int, u32,
+                                                         ctypes.POINTER(sz)]
+    lib.abacus_nf_multipoles.argtypes = [BoxP, ctypes.c_int, BinnedP, ctypes.c_int, u32, vp, vp,
+                                         sz, vp]
+    lib.abacus_nf_kick_drift_workspace_bytes.argtypes = [BoxP, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.abacus_nf_kick_drift.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, vp, vp, vp, vp,
+                                         vp, sz, vp]
+    lib.abacus_nf_timestep.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double]
     for name in EXPORTS:
-        if name != "abacus_nf_strerror":
+        if name not in ("abacus_nf_strerror", "abacus_nf_timestep"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.abacus_nf_timestep.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -112,8 +131,10 @@ def check(code: int, what: str) -> None:
 
 
 def box_array(boxes):
-    """ctypes array of Box from a sequence of (n, box, cpd, radius, eps_plummer)."""
+    """ctypes array of Box from a sequence of (n, box, cpd, radius, eps_plummer[,
+    density_radius])."""
     arr = (Box * len(boxes))()
     for k, b in enumerate(boxes):
-        arr[k] = Box(int(b[0]), float(b[1]), int(b[2]), int(b[3]), float(b[4]))
+        dens = float(b[5]) if len(b) > 5 else 0.0
+        arr[k] = Box(int(b[0]), float(b[1]), int(b[2]), int(b[3]), float(b[4]), dens)
     return arr

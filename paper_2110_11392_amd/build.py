@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libabacus_nf.so")
 ARCH = "gfx950"
 
 SOURCES = ["common.hip", "bin.hip", "plan.hip", "pairs.hip", "vjp.hip", "reduce.hip", "tune.hip",
-           "api.hip"]
+           "multipoles.hip", "kdk.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

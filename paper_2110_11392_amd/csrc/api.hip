@@ -4,6 +4,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -38,12 +39,20 @@ int hip_fail(hipError_t e, const char* what) {
 struct Resolved {
   std::vector<DevBox> boxes;
   int64_t n_total = 0, cells_total = 0, pencils_total = 0, max_box_n = 0;
+  // 2R+1 when every box shares one near-field radius R <= 3 (tail items can be
+  // split into one task per x offset), else 1.
+  int split_slices = 1;
+  // every box carries a density radius, so the density estimate can be asked for
+  bool density_ok = true;
+  bool plummer = false;  // Eq. 2 instead of Eq. 3
+  int64_t kdk_chunks = 0;  // statistics chunks over all boxes
 };
 
 // Step a1: validate every box and derive the kernel constants.
-int resolve(const abacus_nf_box* in, int nboxes, Resolved* out) {
+int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = false) {
   if (!in || nboxes < 1 || nboxes > kMaxBoxes) return ABACUS_NF_EINVAL;
   out->boxes.resize(nboxes);
+  out->plummer = plummer;
   int64_t n_total = 0, cells_total = 0, pencils_total = 0, max_n = 0;
   for (int b = 0; b < nboxes; ++b) {
     const abacus_nf_box& x = in[b];
@@ -70,6 +79,10 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out) {
     d.R = x.radius;
     d.pencil_base = (int32_t)pencils_total;
     d.cells_per_len = cpl;
+    d.width = x.box / (double)K;
+    d.box_len = x.box;
+    d.chunk_base = (int32_t)out->kdk_chunks;
+    out->kdk_chunks += (cells + kKdkChunk - 1) / kKdkChunk;
     d.inv_w2 = (float)iw2;
     d.inv_w3 = (float)iw3;
     d.c0 = (float)(10.0 / (e * e * e));
@@ -78,15 +91,40 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out) {
     d.eps = (float)e;
     d.ha = (float)(12.0 / (e * e * e * e * e));
     d.hb = (float)(-15.0 / (e * e * e * e));
-    // Points of cells two apart on an axis are >= 1 cell apart; with eps below
-    // half a cell no rounding can bring such a pair inside eps.
-    d.far_newton = e < 0.5 ? 1 : 0;
+    if (plummer) {
+      // Eq. 2: f = (r^2 + eps_p^2)^(-3/2) for every pair, eps_p as given
+      const double ep = x.eps_plummer * cpl;
+      d.far_mode = kFarAll;
+      d.guard = (float)(ep * ep);
+    } else {
+      // Points of cells two apart on an axis are >= 1 cell apart; with eps below
+      // half a cell no rounding can bring such a pair inside eps.
+      d.far_mode = e < 0.5 ? kFarApart : kFarNone;
+      d.guard = kTinyR2;
+    }
+    // Optional density radius b: 0 < b <= R cell widths, so that every pair
+    // within b is a near-field pair.
+    if (x.density_radius != 0.0) {
+      const double bh = x.density_radius * cpl;
+      if (!(x.density_radius > 0.0) || !std::isfinite(x.density_radius) ||
+          !(bh <= (double)x.radius) || !(bh * bh >= 1e-30))
+        return ABACUS_NF_EINVAL;
+      d.b2 = (float)(bh * bh + (double)d.guard);
+      d.inv_b2 = (float)(1.0 / (bh * bh));
+      d.dens_far = bh < 0.5 ? 1 : 0;
+    } else {
+      out->density_ok = false;
+    }
     n_total += x.n;
     cells_total += cells;
     pencils_total += K * K;
     if (x.n > max_n) max_n = x.n;
     if (n_total > kMaxIndex || cells_total >= kMaxIndex) return ABACUS_NF_ERANGE;
   }
+  int split_slices = 2 * in[0].radius + 1;
+  for (int b = 1; b < nboxes; ++b)
+    if (in[b].radius != in[0].radius) split_slices = 1;
+  out->split_slices = split_slices <= kMaxSlices ? split_slices : 1;
   out->n_total = n_total;
   out->cells_total = cells_total;
   out->pencils_total = pencils_total;
@@ -102,9 +140,10 @@ struct Layout {
   // binning region
   size_t counts, keys0, keys1, vals0, vals1, hist, hist_scan, bin_scan;
   // force / adjoint region (overlaps the binning region)
-  size_t pencil_counts, item_base, items, item_bucket, item_slot, queue, ctrl, plan_scan, mom, src_w;
+  size_t pencil_counts, item_base, items, item_bucket, item_slot, tasks, ctrl, plan_scan, partial, mom,
+      src_w;
   size_t total;
-  int64_t max_items;
+  int64_t max_items, max_tasks, max_split;
 };
 
 Layout layout(const Resolved& r) {
@@ -136,11 +175,14 @@ Layout layout(const Resolved& r) {
   L.items = take(sizeof(int4) * (size_t)L.max_items);
   L.item_bucket = take(4 * (size_t)L.max_items);
   L.item_slot = take(4 * (size_t)L.max_items);
-  L.queue = take(4 * (size_t)L.max_items);
-  L.ctrl = take(4 * (size_t)(3 * kBuckets + 8));
+  L.max_split = r.split_slices > 1 ? std::min<int64_t>(kMaxSplit, L.max_items) : 0;
+  L.max_tasks = plan_max_tasks(L.max_items, L.max_split);
+  L.tasks = take(4 * (size_t)L.max_tasks);
+  L.ctrl = take(4 * (size_t)kCtrlInts);
+  L.partial = take(sizeof(float) * kPartialStride * kTile * (size_t)(L.max_split * r.split_slices));
   L.plan_scan = take(4 * (size_t)scan_tmp_ints(r.pencils_total));
   L.mom = take(sizeof(double) * 4 * kMomChunks * r.boxes.size());
-  L.src_w = take(2 * sizeof(float4) * (size_t)n);
+  L.src_w = take(6 * sizeof(float) * (size_t)n);  // packed source records
   const size_t force_end = o;
   L.total = bin_end > force_end ? bin_end : force_end;
   return L;
@@ -159,7 +201,7 @@ int check_ws(void* ws, size_t ws_bytes, const Layout& L) {
 
 int acc_mode(uint32_t flags, AccMode* mode) {
   const uint32_t known = ABACUS_NF_SINGLE_ACC | ABACUS_NF_CHUNKED | ABACUS_NF_COMPENSATED |
-                         ABACUS_NF_COUNT_PAIRS;
+                         ABACUS_NF_COUNT_PAIRS | ABACUS_NF_PLUMMER;
   if (flags & ~known) return ABACUS_NF_EINVAL;
   const uint32_t acc = flags & (ABACUS_NF_SINGLE_ACC | ABACUS_NF_CHUNKED | ABACUS_NF_COMPENSATED);
   if (acc == 0 || acc == ABACUS_NF_COMPENSATED) *mode = kAccCompensated;
@@ -188,7 +230,7 @@ TuneKey tune_key(const abacus_nf_box* boxes, int nboxes, const Resolved& r, AccM
   }
   TuneKey k;
   k.kernel = kernel;
-  k.mode = (uint32_t)mode;
+  k.mode = (uint32_t)mode | (r.plummer ? 0x100u : 0u);
   k.nboxes = nboxes;
   k.n_total = r.n_total;
   k.cells_total = r.cells_total;
@@ -204,8 +246,9 @@ struct TimedLaunch {
 std::mutex g_timing_mu;
 bool g_timing = false;
 std::vector<TimedLaunch> g_pending;
-double g_ms[4] = {0, 0, 0, 0};
-int64_t g_launches[4] = {0, 0, 0, 0};
+constexpr int kTimerSlots = 6;  // forward, adjoint, bin, plan, multipoles, kick-drift
+double g_ms[kTimerSlots] = {};
+int64_t g_launches[kTimerSlots] = {};
 
 struct Timer {
   int kernel;
@@ -241,6 +284,12 @@ void drain_timing() {
   g_pending.clear();
 }
 
+// Tail items to split for this launch: about one per resident wave.
+int64_t split_items_for(const KernelConfig& c, AccMode mode, const Resolved& r, const Layout& L) {
+  if (!c.split || mode == kAccSingle || r.split_slices < 2) return 0;
+  return std::min<int64_t>(L.max_split, resident_wave_capacity());
+}
+
 PlanWork plan_work(void* ws, const Layout& L) {
   PlanWork w;
   w.pencil_counts = at<int32_t>(ws, L.pencil_counts);
@@ -248,10 +297,14 @@ PlanWork plan_work(void* ws, const Layout& L) {
   w.items = at<int4>(ws, L.items);
   w.item_bucket = at<int32_t>(ws, L.item_bucket);
   w.item_slot = at<int32_t>(ws, L.item_slot);
-  w.queue = at<int32_t>(ws, L.queue);
+  w.tasks = at<int32_t>(ws, L.tasks);
   w.ctrl = at<int32_t>(ws, L.ctrl);
+  w.partial = at<float>(ws, L.partial);
   w.scan_tmp = at<int32_t>(ws, L.plan_scan);
   w.max_items = L.max_items;
+  w.max_tasks = L.max_tasks;
+  w.max_split = L.max_split;
+  w.split_items = 0;
   return w;
 }
 
@@ -309,33 +362,37 @@ int abacus_nf_bin(const abacus_nf_box* boxes, int nboxes, const float* pos,
 }
 
 int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
-                     float* acc, double* momentum, int64_t* pair_count, uint32_t flags, void* ws,
-                     size_t ws_bytes, void* stream) {
+                     float* acc, float* density, double* momentum, int64_t* pair_count,
+                     uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
   Resolved r;
-  int rc = resolve(boxes, nboxes, &r);
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
   AccMode mode;
   if ((rc = acc_mode(flags, &mode))) return rc;
   const bool count = (flags & ABACUS_NF_COUNT_PAIRS) != 0;
   if (!binned_ok(b) || (r.n_total > 0 && !acc) || (count && !pair_count)) return ABACUS_NF_EINVAL;
+  if (density && (count || !r.density_ok)) return ABACUS_NF_EINVAL;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevBox* dboxes = at<DevBox>(ws, L.boxtab);
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
   if (count) ANF_HIP(fill_i64(pair_count, 0, 1, s), "pair counter");
-  const PlanWork w = plan_work(ws, L);
+  PlanWork w = plan_work(ws, L);
   const KernelConfig cfg = lookup_config(tune_key(boxes, nboxes, r, mode, 0));
+  w.split_items = split_items_for(cfg, mode, r, L);
   {
     Timer t(3, s);
-    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, w, s),
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span,
+                        r.split_slices, w, s),
             "work plan");
     t.done();
   }
   if (r.n_total > 0) {
     Timer t(0, s);
     ANF_HIP(launch_forward(mode, count, cfg, dboxes, w, r.pencils_total, b->cell_offsets, b->rel,
-                           b->perm, acc, pair_count, s),
+                           b->perm, acc, r.n_total > 0 ? density : nullptr, pair_count,
+                           at<float>(ws, L.src_w), r.n_total, s),
             "forward pair kernel");
     t.done();
   }
@@ -349,7 +406,7 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
                          const float* wv, float* grad, uint32_t flags, void* ws, size_t ws_bytes,
                          void* stream) {
   Resolved r;
-  int rc = resolve(boxes, nboxes, &r);
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
   AccMode mode;
   if ((rc = acc_mode(flags, &mode))) return rc;
@@ -360,18 +417,20 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevBox* dboxes = at<DevBox>(ws, L.boxtab);
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
-  const PlanWork w = plan_work(ws, L);
+  PlanWork w = plan_work(ws, L);
   const KernelConfig cfg = lookup_config(tune_key(boxes, nboxes, r, mode, 1));
+  w.split_items = split_items_for(cfg, mode, r, L);
   {
     Timer t(3, s);
-    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, w, s),
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span,
+                        r.split_slices, w, s),
             "work plan");
     t.done();
   }
   if (r.n_total > 0) {
     Timer t(1, s);
     ANF_HIP(launch_vjp(mode, cfg, dboxes, w, r.pencils_total, b->cell_offsets, b->rel, b->perm, wv,
-                       at<float4>(ws, L.src_w), r.n_total, grad, s),
+                       at<float>(ws, L.src_w), r.n_total, grad, s),
             "adjoint pair kernel");
     t.done();
   }
@@ -384,6 +443,7 @@ static abacus_nf_tuning to_public(const KernelConfig& c) {
   t.pipeline = c.pipeline;
   t.span = c.span;
   t.grid_mult = c.grid_mult;
+  t.split = c.split;
   return t;
 }
 
@@ -393,13 +453,14 @@ static KernelConfig from_public(const abacus_nf_tuning& t) {
   c.pipeline = t.pipeline;
   c.span = t.span;
   c.grid_mult = t.grid_mult;
+  c.split = t.split;
   return c;
 }
 
 int abacus_nf_get_tuning(const abacus_nf_box* boxes, int nboxes, uint32_t flags, int kernel,
                          abacus_nf_tuning* out) {
   Resolved r;
-  int rc = resolve(boxes, nboxes, &r);
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
   AccMode mode;
   if ((rc = acc_mode(flags & ~ABACUS_NF_COUNT_PAIRS, &mode))) return rc;
@@ -411,7 +472,7 @@ int abacus_nf_get_tuning(const abacus_nf_box* boxes, int nboxes, uint32_t flags,
 int abacus_nf_set_tuning(const abacus_nf_box* boxes, int nboxes, uint32_t flags, int kernel,
                          const abacus_nf_tuning* t) {
   Resolved r;
-  int rc = resolve(boxes, nboxes, &r);
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
   AccMode mode;
   if ((rc = acc_mode(flags & ~ABACUS_NF_COUNT_PAIRS, &mode))) return rc;
@@ -431,7 +492,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
                        float* scratch, uint32_t flags, void* ws, size_t ws_bytes, void* stream,
                        abacus_nf_tuning* forward_out, abacus_nf_tuning* adjoint_out) {
   Resolved r;
-  int rc = resolve(boxes, nboxes, &r);
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
   AccMode mode;
   if ((rc = acc_mode(flags, &mode))) return rc;
@@ -445,7 +506,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
   if (r.n_total > 0) {
     DevBox* dboxes = at<DevBox>(ws, L.boxtab);
     ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
-    const PlanWork w = plan_work(ws, L);
+    PlanWork w = plan_work(ws, L);
     hipEvent_t e0, e1;
     ANF_HIP(hipEventCreate(&e0), "event");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -458,15 +519,18 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
       float best_ms = 3.0e38f;
       for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
         err = hipEventRecord(e0, s);
+        w.split_items = split_items_for(c, mode, r, L);
         if (err == hipSuccess)
-          err = launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, c.span, w, s);
+          err = launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, c.span,
+                            r.split_slices, w, s);
         if (err == hipSuccess) {
           if (kernel == 0)
             err = launch_forward(mode, false, c, dboxes, w, r.pencils_total, b->cell_offsets,
-                                 b->rel, b->perm, scratch, nullptr, s);
+                                 b->rel, b->perm, scratch, nullptr, nullptr, at<float>(ws, L.src_w),
+                                 r.n_total, s);
           else  // any finite cotangent times the same: read the offsets as w
             err = launch_vjp(mode, c, dboxes, w, r.pencils_total, b->cell_offsets, b->rel,
-                             b->perm, b->rel, at<float4>(ws, L.src_w), r.n_total, scratch, s);
+                             b->perm, b->rel, at<float>(ws, L.src_w), r.n_total, scratch, s);
         }
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -505,6 +569,11 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
         c.grid_mult = 3 - cur.grid_mult;
         try_cfg(c);
       }
+      {
+        KernelConfig c = cur;
+        c.split = 1 - cur.split;
+        try_cfg(c);
+      }
       best[kernel] = cur;
     }
     (void)hipEventDestroy(e0);
@@ -515,6 +584,62 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
   store_config(ka, best[1], true);
   if (forward_out) *forward_out = to_public(best[0]);
   if (adjoint_out) *adjoint_out = to_public(best[1]);
+  return ABACUS_NF_OK;
+}
+
+// ---- cell multipoles ---------------------------------------------------------
+
+struct MpLayout {
+  size_t boxtab, wave_count, wave_base, scan, waves, full, total;
+  int64_t max_waves;
+};
+
+MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
+  MpLayout L;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + (bytes ? bytes : 1));
+    return at;
+  };
+  L.boxtab = take(sizeof(DevBox) * r.boxes.size());
+  L.wave_count = take(4 * (size_t)r.pencils_total);
+  L.wave_base = take(4 * (size_t)(r.pencils_total + 1));
+  L.scan = take(4 * (size_t)scan_tmp_ints(r.pencils_total));
+  // every wave holds at least one cell
+  L.max_waves = r.cells_total;
+  L.waves = take(sizeof(int4) * (size_t)L.max_waves);
+  L.full = reduced ? take(sizeof(double) * (size_t)multipole_terms(order, false) *
+                          (size_t)r.cells_total)
+                   : 0;
+  L.total = o;
+  return L;
+}
+
+struct KdkLayout {
+  size_t boxtab, sumsq, amax, part, total;
+};
+
+KdkLayout kdk_layout(const Resolved& r) {
+  KdkLayout L;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + (bytes ? bytes : 1));
+    return at;
+  };
+  L.boxtab = take(sizeof(DevBox) * r.boxes.size());
+  L.sumsq = take(sizeof(double) * (size_t)r.cells_total);
+  L.amax = take(sizeof(double) * (size_t)r.cells_total);
+  L.part = take(sizeof(double) * 3 * (size_t)r.kdk_chunks);
+  L.total = o;
+  return L;
+}
+
+int mp_args(int order, uint32_t flags, bool* reduced) {
+  if (order < 0 || order > kMaxMultipoleOrder) return ABACUS_NF_EINVAL;
+  if (flags & ~ABACUS_NF_REDUCED) return ABACUS_NF_EINVAL;
+  *reduced = (flags & ABACUS_NF_REDUCED) != 0;
   return ABACUS_NF_OK;
 }
 
@@ -533,6 +658,111 @@ const char* abacus_nf_strerror(int code) {
   }
 }
 
+int abacus_nf_multipole_terms(int order, uint32_t flags, int64_t* terms) {
+  bool reduced = false;
+  int rc = mp_args(order, flags, &reduced);
+  if (rc) return rc;
+  if (!terms) return ABACUS_NF_EINVAL;
+  *terms = multipole_terms(order, reduced);
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_multipoles_workspace_bytes(const abacus_nf_box* boxes, int nboxes, int order,
+                                         uint32_t flags, size_t* bytes) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  bool reduced = false;
+  if ((rc = mp_args(order, flags, &reduced))) return rc;
+  if (!bytes) return ABACUS_NF_EINVAL;
+  *bytes = mp_layout(r, order, reduced).total;
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_multipoles(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                         int order, uint32_t flags, double* out, void* ws, size_t ws_bytes,
+                         void* stream) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  bool reduced = false;
+  if ((rc = mp_args(order, flags, &reduced))) return rc;
+  if (!binned_ok(b) || !out) return ABACUS_NF_EINVAL;
+  const MpLayout L = mp_layout(r, order, reduced);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
+    return ABACUS_NF_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  MpWork w;
+  w.pencils = r.pencils_total;
+  w.wave_count = at<int32_t>(ws, L.wave_count);
+  w.wave_base = at<int32_t>(ws, L.wave_base);
+  w.scan_tmp = at<int32_t>(ws, L.scan);
+  w.waves = at<int4>(ws, L.waves);
+  w.max_waves = L.max_waves;
+  w.full = reduced ? at<double>(ws, L.full) : nullptr;
+  Timer t(4, s);
+  ANF_HIP(launch_multipoles(dboxes, nboxes, r.cells_total, order, reduced, w, b->cell_offsets,
+                            b->rel, out, s),
+          "multipoles");
+  t.done();
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_kick_drift_workspace_bytes(const abacus_nf_box* boxes, int nboxes,
+                                         size_t* bytes) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  if (!bytes) return ABACUS_NF_EINVAL;
+  *bytes = kdk_layout(r).total;
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_kick_drift(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                         const double* kick, const double* drift, float* pos, float* vel,
+                         const float* acc, double* cell_stats, double* box_stats, void* ws,
+                         size_t ws_bytes, void* stream) {
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r);
+  if (rc) return rc;
+  if (!binned_ok(b) || !kick || !drift) return ABACUS_NF_EINVAL;
+  if (r.n_total > 0 && (!pos || !vel || !acc)) return ABACUS_NF_EINVAL;
+  for (int i = 0; i < nboxes; ++i) {
+    if (!std::isfinite(kick[i]) || !std::isfinite(drift[i])) return ABACUS_NF_EINVAL;
+    r.boxes[i].kick = kick[i];
+    r.boxes[i].drift = drift[i];
+  }
+  const KdkLayout L = kdk_layout(r);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
+    return ABACUS_NF_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  KdkWork w;
+  w.cell_sumsq = at<double>(ws, L.sumsq);
+  w.cell_amax = at<double>(ws, L.amax);
+  w.chunk_part = at<double>(ws, L.part);
+  w.chunks = r.kdk_chunks;
+  Timer t(5, s);
+  ANF_HIP(launch_kick_drift(dboxes, nboxes, r.cells_total, w, b->cell_offsets, b->perm, pos, vel,
+                            acc, cell_stats, box_stats, s),
+          "kick-drift");
+  t.done();
+  return ABACUS_NF_OK;
+}
+
+double abacus_nf_timestep(const double* box_stats, double a, double H, double eta_acc,
+                          double eta_H) {
+  if (!box_stats) return NAN;
+  const double global = box_stats[2] > 0.0 ? box_stats[1] / box_stats[2] : INFINITY;
+  const double ratio = box_stats[0] > global ? box_stats[0] : global;
+  const double acc_step = eta_acc * a * H * ratio;
+  const double hubble_step = eta_H * a;
+  return acc_step < hubble_step ? acc_step : hubble_step;
+}
+
 int abacus_nf_timing_enable(int enable) {
   std::lock_guard<std::mutex> lock(g_timing_mu);
   g_timing = enable != 0;
@@ -540,7 +770,7 @@ int abacus_nf_timing_enable(int enable) {
 }
 
 int abacus_nf_timing_read(int kernel, double* ms, int64_t* launches) {
-  if (kernel < 0 || kernel > 3) return ABACUS_NF_EINVAL;
+  if (kernel < 0 || kernel >= kTimerSlots) return ABACUS_NF_EINVAL;
   std::lock_guard<std::mutex> lock(g_timing_mu);
   drain_timing();
   if (ms) *ms = g_ms[kernel];
@@ -551,7 +781,7 @@ int abacus_nf_timing_read(int kernel, double* ms, int64_t* launches) {
 int abacus_nf_timing_reset(void) {
   std::lock_guard<std::mutex> lock(g_timing_mu);
   drain_timing();
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kTimerSlots; ++k) {
     g_ms[k] = 0.0;
     g_launches[k] = 0;
   }

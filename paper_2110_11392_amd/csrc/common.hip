@@ -167,4 +167,13 @@ int persistent_blocks(const void* kernel, int threads) {
   return cus * per_cu;
 }
 
+int resident_wave_capacity() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return cus * 32;
+}
+
 }  // namespace anf

@@ -22,6 +22,14 @@ constexpr int kMaxSpan = 3;
 constexpr int kDefaultSpan = 2;
 // Cost buckets for the longest-first work queue (floor(log2 cost) descending).
 constexpr int kBuckets = 64;
+// ctrl layout (int32): bucket counts [kBuckets], bucket bases [kBuckets], then
+// the task head, task count, whole-item tasks, split items and slices per item.
+constexpr int kCtrlHead = 2 * kBuckets;
+constexpr int kCtrlNTasks = kCtrlHead + 1;
+constexpr int kCtrlNWhole = kCtrlHead + 2;
+constexpr int kCtrlNSplit = kCtrlHead + 3;
+constexpr int kCtrlSlices = kCtrlHead + 4;
+constexpr int kCtrlInts = kCtrlHead + 8;
 // Radix sort: 8-bit digits, 256 threads x 16 keys per block.
 constexpr int kRadixBits = 8;
 constexpr int kRadixThreads = 256;
@@ -36,6 +44,40 @@ constexpr int kMomChunks = 64;
 // r^2 guard: added to every squared separation so that coincident particles
 // (r = 0, including a particle with itself) give a finite f and zero force.
 constexpr float kTinyR2 = 1e-24f;
+
+// Accumulation of a sink's sum (see ABACUS_NF_SINGLE_ACC / CHUNKED / COMPENSATED).
+enum AccMode { kAccSingle = 0, kAccChunked = 1, kAccCompensated = 2 };
+
+// Error-free TwoSum of (a, t): a <- fl(a + t), e accumulates the rounding error.
+__device__ __forceinline__ void two_sum_fold(float& a, float& e, float t) {
+  const float s = a + t;
+  const float bp = s - a;
+  const float ap = s - bp;
+  e += (a - ap) + (t - bp);
+  a = s;
+}
+
+// Fold an x-offset slice (a, e) of a sink's sum into the total (A, E).  The
+// pair kernels and k_combine_slices run this same function in the same slice
+// order, so a sink's bits do not depend on whether its work item was split.
+template <int kAcc>
+__device__ __forceinline__ void slice_fold(float& A, float& E, float a, float e) {
+  if (kAcc == kAccCompensated) {
+    two_sum_fold(A, E, a);
+    E += e;
+  } else {
+    A += a;
+  }
+}
+
+// Work tasks: task = item << kTaskShift | code; code 0 runs the whole item,
+// code c > 0 runs only x offset c - 1 - R (a slice of a split tail item).
+constexpr int kTaskShift = 3;
+constexpr int kTaskCodeMask = 7;
+constexpr int kMaxSlices = 7;      // 2R + 1 for R <= 3; larger R is never split
+constexpr int kMaxSplit = 8192;    // most tail items split per launch
+// Floats kept per lane and slice of a split item: sum and error per axis, density.
+constexpr int kPartialStride = 7;
 
 // Per-box parameters resolved on the host (step a1 of the path) and kept in
 // device memory.  Lengths in the kernels are in cell widths w = L/K.
@@ -52,9 +94,21 @@ struct DevBox {
   float c0, c1, c2;     // f(r) = c0 + c1 r + c2 r^2 for r < eps (cell units), Eq. 3
   float eps;            // eps_s / w
   float ha, hb;         // h(r) = f'(r)/r = ha + hb / r for r < eps (cell units)
-  int32_t far_newton;   // 1 if eps < 1/2 cell: cells >= 2 apart on an axis hold only r > eps pairs
-  int32_t pad_;
+  // Which source cells may use the plain f = (r^2 + guard)^(-3/2) branch:
+  // kFarNone every cell needs the spline select; kFarApart cells >= 2 apart on
+  // some axis (eps < 1/2 cell, so they hold only r > eps pairs); kFarAll every
+  // cell (the Plummer law, Eq. 2).
+  int32_t far_mode;
+  float guard;          // added to every r^2 (cell units): tiny for Eq. 3, eps_p^2 for Eq. 2
+  float b2;             // b^2 + guard, b the top-hat density radius (cell units); 0 if unused
+  float inv_b2;         // 1 / b^2
+  int32_t dens_far;     // 1 if b < 1/2 cell: cells >= 2 apart on an axis hold no pair within b
+  int32_t chunk_base;   // first reduction chunk of the box (kick-drift statistics)
+  double width;         // w = L / K (box units per cell width)
+  double box_len;       // L
+  double kick, drift;   // kick-drift step factors of this call
 };
+constexpr int kFarNone = 0, kFarApart = 1, kFarAll = 2;
 
 constexpr int kBoxChunk = 24;  // boxes per table-writing launch (kernel argument size)
 struct BoxChunk {
@@ -96,6 +150,35 @@ int64_t scan_tmp_ints(int64_t n);
 hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp,
                           hipStream_t s);
 
+// multipoles.hip
+constexpr int kMaxMultipoleOrder = 8;
+struct MpWork {
+  int64_t pencils;
+  int32_t* wave_count;  // pencils: work waves per pencil
+  int32_t* wave_base;   // pencils + 1: exclusive scan; [pencils] = total waves
+  int32_t* scan_tmp;
+  int4* waves;          // max_waves records {first cell, end cell, box, 0}
+  int64_t max_waves;
+  double* full;         // cells_total x complete terms (only for the reduced basis)
+};
+int64_t multipole_terms(int p, bool reduced);
+hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_total, int order,
+                             bool reduced, const MpWork& w, const int32_t* cell_offsets,
+                             const float* rel, double* out, hipStream_t s);
+
+// kdk.hip
+constexpr int kKdkChunk = 8192;  // cells per statistics chunk
+struct KdkWork {
+  double* cell_sumsq;   // cells_total: sum |v'|^2 per cell
+  double* cell_amax;    // cells_total: max |a| per cell
+  double* chunk_part;   // chunks x 3: min ratio, sum |v'|^2, max |a|
+  int64_t chunks;
+};
+hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t cells_total,
+                             const KdkWork& w, const int32_t* cell_offsets, const int32_t* perm,
+                             float* pos, float* vel, const float* acc, double* cell_stats,
+                             double* box_stats, hipStream_t s);
+
 // bin.hip
 struct BinWork {
   int32_t* counts;   // cells_total
@@ -117,18 +200,26 @@ struct PlanWork {
   int4* items;             // max_items
   int32_t* item_bucket;    // max_items: cost bucket of each item
   int32_t* item_slot;      // max_items: position of the item inside its bucket
-  int32_t* queue;          // max_items
-  int32_t* ctrl;           // kBuckets*3 + 8: counts, bases, cursors, head
+  int32_t* tasks;          // max_tasks: item << kTaskShift | code, longest first
+  int32_t* ctrl;           // kCtrlInts
   int32_t* scan_tmp;
+  float* partial;          // split slices: [slot][slice][6][64] (sum and error per axis)
   int64_t max_items;
+  int64_t max_tasks;
+  int64_t max_split;       // capacity of partial in split items
+  int64_t split_items;     // items to split in this launch (0: none)
 };
+int64_t plan_max_tasks(int64_t max_items, int64_t max_split);
 int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_total);
+// w.split_items of the cheapest items are split into `slices` = 2R+1 x-offset
+// tasks (every box must share R <= 3 when w.split_items > 0).
 hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils_total,
-                       const int32_t* cell_offsets, int span, const PlanWork& w, hipStream_t s);
-inline int32_t* plan_head(const PlanWork& w) { return w.ctrl + 3 * kBuckets; }
-inline const int32_t* plan_n_items(const PlanWork& w, int64_t pencils_total) {
-  return w.item_base + pencils_total;
-}
+                       const int32_t* cell_offsets, int span, int slices, const PlanWork& w,
+                       hipStream_t s);
+// Combine the slices of split items into final outputs (adjoint: 1/w^3 scale;
+// density: NULL or the density output of the forward kernel).
+hipError_t launch_combine(AccMode mode, bool adjoint, const DevBox* boxes, const PlanWork& w,
+                          const int32_t* perm, float* out, float* density, hipStream_t s);
 
 // Tunable launch shape of a pair kernel (chosen by the autotuner in tune.hip).
 struct KernelConfig {
@@ -136,6 +227,7 @@ struct KernelConfig {
   int pipeline;   // 1: request the next step's sources before using the current ones
   int span;       // most cells one work item may span (1..3); a planner parameter
   int grid_mult;  // persistent workgroups per resident slot (1 or 2)
+  int split;      // 1: split the cheapest tail items into x-offset slices
 };
 KernelConfig default_config(int kernel);  // kernel 0: forward, 1: adjoint
 bool config_valid(int kernel, const KernelConfig& c);
@@ -153,16 +245,18 @@ void store_config(const TuneKey& k, const KernelConfig& c, bool persist);
 void clear_config(const TuneKey& k);
 
 // pairs.hip
-enum AccMode { kAccSingle = 0, kAccChunked = 1, kAccCompensated = 2 };
+// src3: workspace for n_total packed (x, y, z) source records.
 hipError_t launch_forward(AccMode mode, bool count_pairs, const KernelConfig& cfg,
                           const DevBox* boxes, const PlanWork& w, int64_t pencils_total,
                           const int32_t* cell_offsets, const float* rel, const int32_t* perm,
-                          float* acc, int64_t* pair_count, hipStream_t s);
+                          float* acc, float* density, int64_t* pair_count, float* src3,
+                          int64_t n_total, hipStream_t s);
 
 // vjp.hip
+// src6: workspace for n_total packed (x, y, z, w_x, w_y, w_z) source records.
 hipError_t launch_vjp(AccMode mode, const KernelConfig& cfg, const DevBox* boxes,
                       const PlanWork& w, int64_t pencils_total, const int32_t* cell_offsets,
-                      const float* rel, const int32_t* perm, const float* wvec, float4* src_w,
+                      const float* rel, const int32_t* perm, const float* wvec, float* src6,
                       int64_t n_total, float* grad, hipStream_t s);
 
 // reduce.hip
@@ -171,5 +265,7 @@ hipError_t launch_momentum(const DevBox* boxes, int nboxes, int64_t max_box_n, c
 
 // Occupancy-sized persistent grid for a kernel (cached per device and kernel).
 int persistent_blocks(const void* kernel, int threads);
+// Wavefronts the current device can hold at full occupancy (CUs x 32).
+int resident_wave_capacity();
 
 }  // namespace anf

@@ -25,39 +25,6 @@ namespace anf {
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// One interaction: t += f(|d|) d with d = s - q (cell units).  kNear: the pair
-// may lie inside the softening length, so f = min(spline(r), 1/r^3); otherwise
-// the source cell is so far from every sink that r > eps for all its pairs and
-// f = 1/r^3 -- exactly the value the minimum would select.
-template <bool kNear>
-__device__ __forceinline__ void interact(const float4 s, float qx, float qy, float qz, float c0,
-                                         float c1, float c2, float& tx, float& ty, float& tz) {
-  const float dx = s.x - qx;
-  const float dy = s.y - qy;
-  const float dz = s.z - qz;
-  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, kTinyR2)));
-  const float rinv = rsq(r2);
-  const float rinv3 = (rinv * rinv) * rinv;
-  float f = rinv3;
-  if (kNear) {
-    const float r = r2 * rinv;
-    const float spline = __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0);
-    f = __builtin_fminf(spline, rinv3);
-  }
-  tx = __builtin_fmaf(f, dx, tx);
-  ty = __builtin_fmaf(f, dy, ty);
-  tz = __builtin_fmaf(f, dz, tz);
-}
-
-// Error-free TwoSum of (a, t): a <- fl(a + t), e accumulates the rounding error.
-__device__ __forceinline__ void two_sum_fold(float& a, float& e, float t) {
-  const float s = a + t;
-  const float bp = s - a;
-  const float ap = s - bp;
-  e += (a - ap) + (t - bp);
-  a = s;
-}
-
 __device__ __forceinline__ int wrap1(int v, int K) {
   v += v < 0 ? K : 0;
   v -= v >= K ? K : 0;
@@ -66,72 +33,142 @@ __device__ __forceinline__ int wrap1(int v, int K) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Sum the sources [beg, end) into (tx, ty, tz), kU per step.  With kPipe the
-// next kU sources are requested before the current ones are used, so the
-// scalar-cache latency of one group overlaps the arithmetic of the previous.
-template <int kU, bool kPipe, bool kNear>
-__device__ __forceinline__ void sum_sources(const float4* __restrict__ rel, int beg, int end,
-                                            float qx, float qy, float qz, float c0, float c1,
-                                            float c2, float& tx, float& ty, float& tz) {
+// Per-item constants of the pair law: f(r) = c0 + c1 r + c2 r^2 inside eps
+// (cell units, Eq. 3) and the squared top-hat radius b2 of the density estimate.
+struct PairConst {
+  float c0, c1, c2, b2, g;
+};
+
+// One interaction: t += f(|d|) d with d = s - q (cell units) and r^2 taken with
+// the guard g added.  kNear: the pair may lie inside the spline's softening
+// length, so f = min(spline(r), 1/r^3); otherwise f = (r^2 + g)^(-3/2): for Eq. 3
+// the source cell is so far from every sink that r > eps for all its pairs and
+// this is exactly the value the minimum would select; for Eq. 2 (g = eps_p^2)
+// it is the Plummer law itself.  kDens also adds the apodized top-hat weight
+// max(b^2 - r^2, 0) of Sec. 3.4.4 to rho (b2 carries the same guard).
+template <bool kNear, bool kDens>
+__device__ __forceinline__ void interact(float sx, float sy, float sz, float qx, float qy,
+                                         float qz, const PairConst& k, float& tx, float& ty,
+                                         float& tz, float& rho) {
+  const float dx = sx - qx;
+  const float dy = sy - qy;
+  const float dz = sz - qz;
+  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, k.g)));
+  const float rinv = rsq(r2);
+  const float rinv3 = (rinv * rinv) * rinv;
+  float f = rinv3;
+  if (kNear) {
+    const float r = r2 * rinv;
+    const float spline = __builtin_fmaf(__builtin_fmaf(k.c2, r, k.c1), r, k.c0);
+    f = __builtin_fminf(spline, rinv3);
+  }
+  tx = __builtin_fmaf(f, dx, tx);
+  ty = __builtin_fmaf(f, dy, ty);
+  tz = __builtin_fmaf(f, dz, tz);
+  if (kDens) rho += __builtin_fmaxf(k.b2 - r2, 0.0f);
+}
+
+// Sum the sources [beg, end) into (tx, ty, tz) (and rho), kU per step.  Sources
+// are packed (x, y, z) records of 12 bytes so that a group of kU sources
+// occupies 3 kU SGPRs.  With kPipe the next kU sources are requested before the
+// current ones are used, so the scalar-cache latency of one group overlaps the
+// arithmetic of the previous.
+template <int kU, bool kPipe, bool kNear, bool kDens>
+__device__ __forceinline__ void sum_sources(const float* __restrict__ src3, int beg, int end,
+                                            float qx, float qy, float qz, const PairConst& k,
+                                            float& tx, float& ty, float& tz, float& rho) {
   int j = beg;
   if (kPipe && j + kU <= end) {
-    float4 cur[kU];
+    float cur[3 * kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) cur[u] = rel[j + u];
+    for (int u = 0; u < 3 * kU; ++u) cur[u] = src3[3 * j + u];
     for (; j + 2 * kU <= end; j += kU) {
-      float4 nxt[kU];
+      float nxt[3 * kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) nxt[u] = rel[j + kU + u];
+      for (int u = 0; u < 3 * kU; ++u) nxt[u] = src3[3 * (j + kU) + u];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) interact<kNear>(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+      for (int u = 0; u < kU; ++u)
+        interact<kNear, kDens>(cur[3 * u], cur[3 * u + 1], cur[3 * u + 2], qx, qy, qz, k, tx, ty,
+                               tz, rho);
 #pragma unroll
-      for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
+      for (int u = 0; u < 3 * kU; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) interact<kNear>(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+    for (int u = 0; u < kU; ++u)
+      interact<kNear, kDens>(cur[3 * u], cur[3 * u + 1], cur[3 * u + 2], qx, qy, qz, k, tx, ty, tz,
+                             rho);
     j += kU;
   }
   for (; j + kU <= end; j += kU) {
-    float4 cur[kU];
+    float cur[3 * kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) cur[u] = rel[j + u];
+    for (int u = 0; u < 3 * kU; ++u) cur[u] = src3[3 * j + u];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) interact<kNear>(cur[u], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+    for (int u = 0; u < kU; ++u)
+      interact<kNear, kDens>(cur[3 * u], cur[3 * u + 1], cur[3 * u + 2], qx, qy, qz, k, tx, ty, tz,
+                             rho);
   }
-  for (; j < end; ++j) interact<kNear>(rel[j], qx, qy, qz, c0, c1, c2, tx, ty, tz);
+  for (; j < end; ++j)
+    interact<kNear, kDens>(src3[3 * j], src3[3 * j + 1], src3[3 * j + 2], qx, qy, qz, k, tx, ty,
+                           tz, rho);
 }
 
-template <int kAcc, bool kCount, int kU, bool kPipe>
+// Packed 12-byte source records (x, y, z) from the binned float4 offsets.
+__global__ __launch_bounds__(256) void k_pack_sources(const float4* __restrict__ rel, int64_t n,
+                                                      float* __restrict__ src3) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const float4 r = rel[s];
+  src3[3 * s + 0] = r.x;
+  src3[3 * s + 1] = r.y;
+  src3[3 * s + 2] = r.z;
+}
+
+template <int kAcc, bool kCount, int kU, bool kPipe, bool kDens>
 __global__ __launch_bounds__(256) void k_pair_forward(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
-    const int32_t* __restrict__ queue, const int32_t* __restrict__ n_items_ptr,
-    int32_t* __restrict__ head, const int32_t* __restrict__ off, const float4* __restrict__ rel,
-    const int32_t* __restrict__ perm, float* __restrict__ acc_out,
+    const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
+    const int32_t* __restrict__ off, const float4* __restrict__ rel,
+    const float* __restrict__ src3, const int32_t* __restrict__ perm, float* __restrict__ acc_out,
+    float* __restrict__ dens_out, float* __restrict__ partial,
     unsigned long long* __restrict__ pair_count) {
   const int lane = threadIdx.x & 63;
-  const int n_items = uniform(*n_items_ptr);
+  const int n_tasks = uniform(ctrl[kCtrlNTasks]);
+  const int n_whole = uniform(ctrl[kCtrlNWhole]);
+  const int n_split = uniform(ctrl[kCtrlNSplit]);
+  const int slices = uniform(ctrl[kCtrlSlices]);
   while (true) {
     // Every lane takes part in the atomic (lane 0 adds 1, the others 0) so no
     // divergent branch precedes the wave-uniform exit test below.
-    int q = atomicAdd(head, lane == 0 ? 1 : 0);
-    q = uniform(__shfl(q, 0, 64));
-    if (q >= n_items) break;
-    const int4 it = items[uniform(queue[q])];
+    int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
+    t = uniform(__shfl(t, 0, 64));
+    if (t >= n_tasks) break;
+    const int task = uniform(tasks[t]);
+    const int code = task & kTaskCodeMask;  // 0: whole item; c > 0: x offset c - 1 - R only
+    const int4 it = items[task >> kTaskShift];
     const int b = uniform(it.x & 0xffff), count = uniform(it.x >> 16);
     const int cx = uniform(it.y & 0xffff), cy = uniform(it.y >> 16);
     const int za = uniform(it.z & 0xffff), zb = uniform(it.z >> 16);
     const int first = uniform(it.w);
     const int K = uniform(boxes[b].K), R = uniform(boxes[b].R);
     const int cbase = uniform(boxes[b].cell_base);
-    const float c0 = boxes[b].c0, c2 = boxes[b].c2;
+    PairConst kc;
+    kc.c0 = boxes[b].c0;
+    kc.c1 = boxes[b].c1;
+    kc.c2 = boxes[b].c2;
+    kc.b2 = boxes[b].b2;
+    kc.g = boxes[b].guard;
     // c1 meets an SGPR operand (c2) in the spline FMA; a VALU instruction reads
     // at most one SGPR, so keep c1 in a VGPR for the whole item.
-    float c1 = boxes[b].c1;
-    asm volatile("" : "+v"(c1));
+    asm volatile("" : "+v"(kc.c1));
     const int pencil0 = cbase + (cx * K + cy) * K;
     // Cells two or more apart on some axis are >= 1 cell width apart, so with
-    // eps < 1/2 cell every pair in them is Newtonian (f = 1/r^3).
-    const bool far_ok = uniform(boxes[b].far_newton) != 0;
+    // eps < 1/2 cell every pair in them is Newtonian (f = 1/r^3), and with
+    // b < 1/2 cell none of them is within the density radius.
+    const int far_mode = uniform(boxes[b].far_mode);
+    const bool dens_far = kDens && uniform(boxes[b].dens_far) != 0;
+    const int ox_lo = code ? code - 1 - R : -R;
+    const int ox_hi = code ? ox_lo : R;
 
     // ---- which sink this lane owns -------------------------------------
     // lane -> sink: the item's sinks are the contiguous slots [first, first+count)
@@ -143,9 +180,13 @@ __global__ __launch_bounds__(256) void k_pair_forward(
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) p = rel[s];
 
-    float ax = 0.f, ay = 0.f, az = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+    // (A, E): the sink's sum; (a, e): the current x-offset slice (SINGLE keeps
+    // one running accumulator in a and never folds).
+    float Ax = 0.f, Ay = 0.f, Az = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f, Rho = 0.f;
+    float ax = 0.f, ay = 0.f, az = 0.f, ex = 0.f, ey = 0.f, ez = 0.f, rho = 0.f;
     long long npairs = 0;
-    for (int ox = -R; ox <= R; ++ox) {
+    for (int ox = ox_lo; ox <= ox_hi; ++ox) {
+      if (kAcc != kAccSingle) ax = ay = az = ex = ey = ez = rho = 0.f;
       const int sx = wrap1(cx + ox, K);
       const float qx = p.x - (float)ox;
       for (int oy = -R; oy <= R; ++oy) {
@@ -158,24 +199,31 @@ __global__ __launch_bounds__(256) void k_pair_forward(
           const int beg = uniform(off[col + sz]), end = uniform(off[col + sz + 1]);
           if (beg == end) continue;
           const int oz = zu - lane_z;
-          // Wave-uniform: can any pair of this source cell fall inside eps?
-          const bool near = !far_ok || (col_near && zu >= za - 1 && zu <= zb + 1);
+          // Wave-uniform: is this source cell within one cell of every sink
+          // cell of the item, and can a pair of it fall inside the spline?
+          const bool geo_near = col_near && zu >= za - 1 && zu <= zb + 1;
+          const bool near = far_mode == kFarNone || (far_mode == kFarApart && geo_near);
+          const bool dens_here = kDens && (geo_near || !dens_far);
           if (active && oz >= -R && oz <= R) {
             const float qz = p.z - (float)oz;
             if (kCount) npairs += end - beg;
             if (kAcc == kAccSingle) {
               if (near)
-                sum_sources<kU, kPipe, true>(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
+                sum_sources<kU, kPipe, true, kDens>(src3, beg, end, qx, qy, qz, kc, ax, ay, az, rho);
+              else if (dens_here)
+                sum_sources<kU, kPipe, false, kDens>(src3, beg, end, qx, qy, qz, kc, ax, ay, az, rho);
               else
-                sum_sources<kU, kPipe, false>(rel, beg, end, qx, qy, qz, c0, c1, c2, ax, ay, az);
+                sum_sources<kU, kPipe, false, false>(src3, beg, end, qx, qy, qz, kc, ax, ay, az, rho);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
                 if (near)
-                  sum_sources<kU, kPipe, true>(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
+                  sum_sources<kU, kPipe, true, kDens>(src3, cb, ce, qx, qy, qz, kc, tx, ty, tz, rho);
+                else if (dens_here)
+                  sum_sources<kU, kPipe, false, kDens>(src3, cb, ce, qx, qy, qz, kc, tx, ty, tz, rho);
                 else
-                  sum_sources<kU, kPipe, false>(rel, cb, ce, qx, qy, qz, c0, c1, c2, tx, ty, tz);
+                  sum_sources<kU, kPipe, false, false>(src3, cb, ce, qx, qy, qz, kc, tx, ty, tz, rho);
                 if (kAcc == kAccChunked) {
                   ax += tx; ay += ty; az += tz;
                 } else {
@@ -188,68 +236,106 @@ __global__ __launch_bounds__(256) void k_pair_forward(
           }
         }
       }
+      if (kAcc != kAccSingle && code == 0) {
+        slice_fold<kAcc>(Ax, Ex, ax, ex);
+        slice_fold<kAcc>(Ay, Ey, ay, ey);
+        slice_fold<kAcc>(Az, Ez, az, ez);
+        Rho += rho;
+      }
     }
-    if (active) {
-      const float iw2 = boxes[b].inv_w2;
-      const int64_t i = perm[s];
-      acc_out[3 * i + 0] = (ax + ex) * iw2;
-      acc_out[3 * i + 1] = (ay + ey) * iw2;
-      acc_out[3 * i + 2] = (az + ez) * iw2;
+    if (kAcc == kAccSingle) {
+      Ax = ax; Ay = ay; Az = az; Rho = rho;
+    }
+    if (code == 0) {
+      if (active) {
+        const float iw2 = boxes[b].inv_w2;
+        const int64_t i = perm[s];
+        acc_out[3 * i + 0] = (Ax + Ex) * iw2;
+        acc_out[3 * i + 1] = (Ay + Ey) * iw2;
+        acc_out[3 * i + 2] = (Az + Ez) * iw2;
+        if (kDens) dens_out[i] = Rho * boxes[b].inv_b2;
+      }
+    } else {
+      // a tail item split by x offset: keep this slice for k_combine_slices
+      const int slot = (t - n_whole) % n_split;
+      float* dst = partial + (int64_t)(slot * slices + (code - 1)) * kPartialStride * kTile + lane;
+      dst[0 * kTile] = ax; dst[1 * kTile] = ay; dst[2 * kTile] = az;
+      dst[3 * kTile] = ex; dst[4 * kTile] = ey; dst[5 * kTile] = ez;
+      dst[6 * kTile] = rho;
     }
     if (kCount) {
-      if (active) npairs -= 1;  // the sink itself sits in its own cell
+      // the sink itself sits in its own cell, visited by the x offset 0
+      if (active && ox_lo <= 0 && ox_hi >= 0) npairs -= 1;
       for (int d = 32; d >= 1; d >>= 1) npairs += __shfl_xor(npairs, d, 64);
       if (lane == 0) atomicAdd(pair_count, (unsigned long long)npairs);
     }
   }
 }
 
-template <int kAcc, bool kCount, int kU, bool kPipe>
-static hipError_t launch_forward_t(const DevBox* boxes, const PlanWork& w, int64_t pencils,
-                                   const int32_t* off, const float* rel, const int32_t* perm,
-                                   float* acc, int64_t* pair_count, int grid_mult, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&k_pair_forward<kAcc, kCount, kU, kPipe>);
+template <int kAcc, bool kCount, int kU, bool kPipe, bool kDens>
+static hipError_t launch_forward_t(const DevBox* boxes, const PlanWork& w, const int32_t* off,
+                                   const float* rel, const float* src3, const int32_t* perm,
+                                   float* acc, float* dens, int64_t* pair_count, int grid_mult,
+                                   hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_pair_forward<kAcc, kCount, kU, kPipe, kDens>);
   const int blocks = persistent_blocks(fn, 256) * grid_mult;
-  hipLaunchKernelGGL((k_pair_forward<kAcc, kCount, kU, kPipe>), dim3(blocks), dim3(256), 0, s,
-                     boxes, w.items, w.queue, w.item_base + pencils, plan_head(w), off,
-                     reinterpret_cast<const float4*>(rel), perm, acc,
+  hipLaunchKernelGGL((k_pair_forward<kAcc, kCount, kU, kPipe, kDens>), dim3(blocks), dim3(256), 0,
+                     s, boxes, w.items, w.tasks, w.ctrl, off, reinterpret_cast<const float4*>(rel),
+                     src3, perm, acc, dens, w.partial,
                      reinterpret_cast<unsigned long long*>(pair_count));
   return hipGetLastError();
 }
 
-template <int kAcc, bool kCount>
+template <int kAcc, bool kCount, bool kDens>
 static hipError_t dispatch_variant(const KernelConfig& cfg, const DevBox* boxes, const PlanWork& w,
-                                   int64_t pencils, const int32_t* off, const float* rel,
-                                   const int32_t* perm, float* acc, int64_t* pc, hipStream_t s) {
+                                   const int32_t* off, const float* rel, const float* src3,
+                                   const int32_t* perm, float* acc, float* dens, int64_t* pc,
+                                   hipStream_t s) {
   const int g = cfg.grid_mult;
   switch (cfg.unroll * 2 + (cfg.pipeline ? 1 : 0)) {
-    case 4: return launch_forward_t<kAcc, kCount, 2, false>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
-    case 5: return launch_forward_t<kAcc, kCount, 2, true>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
-    case 9: return launch_forward_t<kAcc, kCount, 4, true>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
-    case 16: return launch_forward_t<kAcc, kCount, 8, false>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
-    case 17: return launch_forward_t<kAcc, kCount, 8, true>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
-    default: return launch_forward_t<kAcc, kCount, 4, false>(boxes, w, pencils, off, rel, perm, acc, pc, g, s);
+    case 4: return launch_forward_t<kAcc, kCount, 2, false, kDens>(boxes, w, off, rel, src3, perm, acc, dens, pc, g, s);
+    case 5: return launch_forward_t<kAcc, kCount, 2, true, kDens>(boxes, w, off, rel, src3, perm, acc, dens, pc, g, s);
+    case 9: return launch_forward_t<kAcc, kCount, 4, true, kDens>(boxes, w, off, rel, src3, perm, acc, dens, pc, g, s);
+    case 16: return launch_forward_t<kAcc, kCount, 8, false, kDens>(boxes, w, off, rel, src3, perm, acc, dens, pc, g, s);
+    case 17: return launch_forward_t<kAcc, kCount, 8, true, kDens>(boxes, w, off, rel, src3, perm, acc, dens, pc, g, s);
+    default: return launch_forward_t<kAcc, kCount, 4, false, kDens>(boxes, w, off, rel, src3, perm, acc, dens, pc, g, s);
   }
+}
+
+template <int kAcc>
+static hipError_t dispatch_mode(bool count_pairs, const KernelConfig& cfg, const DevBox* boxes,
+                                const PlanWork& w, const int32_t* off, const float* rel,
+                                const float* src3, const int32_t* perm, float* acc, float* dens,
+                                int64_t* pc, hipStream_t s) {
+  // The debug pair counter is a correctness tool: one fixed kernel variant, no density.
+  if (count_pairs)
+    return dispatch_variant<kAcc, true, false>(default_config(0), boxes, w, off, rel, src3, perm,
+                                               acc, nullptr, pc, s);
+  if (dens)
+    return dispatch_variant<kAcc, false, true>(cfg, boxes, w, off, rel, src3, perm, acc, dens,
+                                               nullptr, s);
+  return dispatch_variant<kAcc, false, false>(cfg, boxes, w, off, rel, src3, perm, acc, nullptr,
+                                              nullptr, s);
 }
 
 hipError_t launch_forward(AccMode mode, bool count_pairs, const KernelConfig& cfg,
                           const DevBox* boxes, const PlanWork& w, int64_t pencils,
                           const int32_t* off, const float* rel, const int32_t* perm, float* acc,
-                          int64_t* pair_count, hipStream_t s) {
-  if (count_pairs) {
-    // The debug counter is a correctness tool: one fixed variant per mode.
-    const KernelConfig base = default_config(0);
-    switch (mode) {
-      case kAccSingle: return dispatch_variant<kAccSingle, true>(base, boxes, w, pencils, off, rel, perm, acc, pair_count, s);
-      case kAccChunked: return dispatch_variant<kAccChunked, true>(base, boxes, w, pencils, off, rel, perm, acc, pair_count, s);
-      default: return dispatch_variant<kAccCompensated, true>(base, boxes, w, pencils, off, rel, perm, acc, pair_count, s);
-    }
-  }
+                          float* density, int64_t* pair_count, float* src3, int64_t n_total,
+                          hipStream_t s) {
+  (void)pencils;
+  if (n_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_sources, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(rel), n_total, src3);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   switch (mode) {
-    case kAccSingle: return dispatch_variant<kAccSingle, false>(cfg, boxes, w, pencils, off, rel, perm, acc, nullptr, s);
-    case kAccChunked: return dispatch_variant<kAccChunked, false>(cfg, boxes, w, pencils, off, rel, perm, acc, nullptr, s);
-    default: return dispatch_variant<kAccCompensated, false>(cfg, boxes, w, pencils, off, rel, perm, acc, nullptr, s);
+    case kAccSingle: e = dispatch_mode<kAccSingle>(count_pairs, cfg, boxes, w, off, rel, src3, perm, acc, density, pair_count, s); break;
+    case kAccChunked: e = dispatch_mode<kAccChunked>(count_pairs, cfg, boxes, w, off, rel, src3, perm, acc, density, pair_count, s); break;
+    default: e = dispatch_mode<kAccCompensated>(count_pairs, cfg, boxes, w, off, rel, src3, perm, acc, density, pair_count, s); break;
   }
+  if (e != hipSuccess) return e;
+  return launch_combine(mode, false, boxes, w, perm, acc, density, s);
 }
 
 }  // namespace anf

@@ -10,7 +10,9 @@
 // all 64 lanes busy where cells hold fewer than 64 particles.
 //
 // Items are queued longest first (bucketed by floor(log2 cost), cost = number
-// of sources the wave visits) so the persistent grid drains evenly.
+// of sources the wave visits) so the persistent grid drains evenly; the
+// cheapest items at the end are split into one task per x offset so the last
+// tasks are short and the grid's tail shrinks.
 #include "nf_internal.h"
 
 namespace anf {
@@ -129,26 +131,95 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
   }
 }
 
-// ctrl layout: [0, B) counts, [B, 2B) bases, [2B, 3B) cursors, [3B] queue head.
-__global__ void k_bucket_scan(int32_t* __restrict__ ctrl) {
+// Bucket bases (longest first) and the task-list layout: the cheapest
+// split_items items of the queue are split into `slices` x-offset tasks each.
+__global__ void k_bucket_scan(int32_t* __restrict__ ctrl, const int32_t* __restrict__ n_items_ptr,
+                              int split_items, int slices) {
   if (threadIdx.x != 0) return;
   int run = 0;
   for (int k = 0; k < kBuckets; ++k) {
     ctrl[kBuckets + k] = run;
     run += ctrl[k];
-    ctrl[2 * kBuckets + k] = 0;
   }
-  ctrl[3 * kBuckets] = 0;
+  const int n_items = *n_items_ptr;
+  int split = slices >= 2 ? split_items : 0;
+  split = split < n_items / 2 ? split : n_items / 2;
+  ctrl[kCtrlHead] = 0;
+  ctrl[kCtrlNWhole] = n_items - split;
+  ctrl[kCtrlNSplit] = split;
+  ctrl[kCtrlSlices] = split > 0 ? slices : 1;
+  ctrl[kCtrlNTasks] = n_items - split + split * (split > 0 ? slices : 1);
 }
 
-__global__ __launch_bounds__(256) void k_bucket_scatter(const int32_t* __restrict__ n_items_ptr,
-                                                        const int32_t* __restrict__ bucket_of,
-                                                        const int32_t* __restrict__ slot_of,
-                                                        const int32_t* __restrict__ ctrl,
-                                                        int32_t* __restrict__ queue) {
+// Item q goes to queue position bases[bucket] + slot; whole items keep their
+// position as a task, split items fan out to one task per slice (slice-major,
+// so the slices of one item are spread over the end of the list).
+__global__ __launch_bounds__(256) void k_task_scatter(const int32_t* __restrict__ n_items_ptr,
+                                                      const int32_t* __restrict__ bucket_of,
+                                                      const int32_t* __restrict__ slot_of,
+                                                      const int32_t* __restrict__ ctrl,
+                                                      int32_t* __restrict__ tasks) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= *n_items_ptr) return;
-  queue[ctrl[kBuckets + bucket_of[q]] + slot_of[q]] = q;
+  const int pos = ctrl[kBuckets + bucket_of[q]] + slot_of[q];
+  const int n_whole = ctrl[kCtrlNWhole];
+  if (pos < n_whole) {
+    tasks[pos] = q << kTaskShift;
+    return;
+  }
+  const int split = ctrl[kCtrlNSplit], slices = ctrl[kCtrlSlices];
+  const int slot = pos - n_whole;
+  for (int c = 1; c <= slices; ++c) tasks[n_whole + (c - 1) * split + slot] = (q << kTaskShift) | c;
+}
+
+// Final outputs of split items: fold the slices in x-offset order with the
+// same slice_fold the pair kernels use for whole items.
+template <int kAcc>
+__global__ __launch_bounds__(64) void k_combine_slices(const DevBox* __restrict__ boxes,
+                                                       const int4* __restrict__ items,
+                                                       const int32_t* __restrict__ tasks,
+                                                       const int32_t* __restrict__ ctrl,
+                                                       const int32_t* __restrict__ perm,
+                                                       const float* __restrict__ partial,
+                                                       int adjoint, float* __restrict__ out,
+                                                       float* __restrict__ density) {
+  const int slot = blockIdx.x;
+  const int split = ctrl[kCtrlNSplit];
+  if (slot >= split) return;
+  const int slices = ctrl[kCtrlSlices];
+  const int task = tasks[ctrl[kCtrlNWhole] + slot];
+  const int4 it = items[task >> kTaskShift];
+  const int lane = threadIdx.x;
+  const int count = it.x >> 16;
+  if (lane >= count) return;
+  const DevBox& B = boxes[it.x & 0xffff];
+  float A[3] = {0.f, 0.f, 0.f}, E[3] = {0.f, 0.f, 0.f}, rho = 0.f;
+  for (int c = 0; c < slices; ++c) {
+    const float* src = partial + (int64_t)(slot * slices + c) * kPartialStride * kTile + lane;
+    for (int k = 0; k < 3; ++k) slice_fold<kAcc>(A[k], E[k], src[k * kTile], src[(3 + k) * kTile]);
+    rho += src[6 * kTile];
+  }
+  const float scale = adjoint ? B.inv_w3 : B.inv_w2;
+  const int64_t i = perm[it.w + lane];
+  for (int k = 0; k < 3; ++k) out[3 * i + k] = (A[k] + E[k]) * scale;
+  if (density) density[i] = rho * B.inv_b2;
+}
+
+hipError_t launch_combine(AccMode mode, bool adjoint, const DevBox* boxes, const PlanWork& w,
+                          const int32_t* perm, float* out, float* density, hipStream_t s) {
+  if (w.split_items <= 0 || mode == kAccSingle) return hipSuccess;
+  const dim3 grid((unsigned)w.split_items);
+  if (mode == kAccChunked)
+    hipLaunchKernelGGL(k_combine_slices<kAccChunked>, grid, dim3(kTile), 0, s, boxes, w.items,
+                       w.tasks, w.ctrl, perm, w.partial, adjoint ? 1 : 0, out, density);
+  else
+    hipLaunchKernelGGL(k_combine_slices<kAccCompensated>, grid, dim3(kTile), 0, s, boxes, w.items,
+                       w.tasks, w.ctrl, perm, w.partial, adjoint ? 1 : 0, out, density);
+  return hipGetLastError();
+}
+
+int64_t plan_max_tasks(int64_t max_items, int64_t max_split) {
+  return max_items + max_split * (kMaxSlices - 1);
 }
 
 int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_total) {
@@ -165,7 +236,7 @@ int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_tot
   } while (0)
 
 hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils, const int32_t* off,
-                       int span, const PlanWork& w, hipStream_t s) {
+                       int span, int slices, const PlanWork& w, hipStream_t s) {
   span = span < 1 ? 1 : (span > kMaxSpan ? kMaxSpan : span);
   const unsigned gp = (unsigned)((pencils + 63) / 64);
   hipLaunchKernelGGL(k_plan_count, dim3(gp), dim3(64), 0, s, boxes, nboxes, pencils, off, span,
@@ -181,10 +252,12 @@ hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils, const i
   hipLaunchKernelGGL(k_item_cost, dim3(gi), dim3(256), 0, s, boxes, w.items, n_items, off,
                      w.item_bucket, w.item_slot, w.ctrl);
   ANF_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, s, w.ctrl);
+  const int split = (int)(w.split_items < w.max_split ? w.split_items : w.max_split);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, s, w.ctrl, n_items,
+                     slices >= 2 && slices <= kMaxSlices ? split : 0, slices);
   ANF_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(gi), dim3(256), 0, s, n_items, w.item_bucket,
-                     w.item_slot, w.ctrl, w.queue);
+  hipLaunchKernelGGL(k_task_scatter, dim3(gi), dim3(256), 0, s, n_items, w.item_bucket,
+                     w.item_slot, w.ctrl, w.tasks);
   return hipGetLastError();
 }
 

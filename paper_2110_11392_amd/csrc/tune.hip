@@ -19,6 +19,7 @@ KernelConfig default_config(int kernel) {
   c.pipeline = 0;
   c.span = kDefaultSpan;
   c.grid_mult = 1;
+  c.split = 1;
   return c;
 }
 
@@ -26,7 +27,8 @@ bool config_valid(int kernel, const KernelConfig& c) {
   const bool unroll_ok = kernel == 0 ? (c.unroll == 2 || c.unroll == 4 || c.unroll == 8)
                                      : (c.unroll == 2 || c.unroll == 4);
   return unroll_ok && (c.pipeline == 0 || c.pipeline == 1) && c.span >= 1 &&
-         c.span <= kMaxSpan && (c.grid_mult == 1 || c.grid_mult == 2);
+         c.span <= kMaxSpan && (c.grid_mult == 1 || c.grid_mult == 2) &&
+         (c.split == 0 || c.split == 1);
 }
 
 namespace {
@@ -63,7 +65,7 @@ const char* cache_path() {
   return (p && *p) ? p : nullptr;
 }
 
-// One line per entry: arch kernel mode nboxes n cells hash unroll pipeline span grid
+// One line per entry: arch kernel mode nboxes n cells hash unroll pipeline span grid split
 void load_cache_locked() {
   if (g_cache_loaded) return;
   g_cache_loaded = true;
@@ -77,8 +79,9 @@ void load_cache_locked() {
   long long n, cells;
   unsigned long long hash;
   KernelConfig c;
-  while (std::fscanf(f, "%63s %d %u %d %lld %lld %llu %d %d %d %d", arch, &kernel, &mode, &nboxes,
-                     &n, &cells, &hash, &c.unroll, &c.pipeline, &c.span, &c.grid_mult) == 11) {
+  while (std::fscanf(f, "%63s %d %u %d %lld %lld %llu %d %d %d %d %d", arch, &kernel, &mode,
+                     &nboxes, &n, &cells, &hash, &c.unroll, &c.pipeline, &c.span, &c.grid_mult,
+                     &c.split) == 12) {
     if (config_valid(kernel, c))
       g_table[Key(arch, kernel, mode, nboxes, n, cells, hash)] = c;
   }
@@ -103,9 +106,10 @@ void store_config(const TuneKey& k, const KernelConfig& c, bool persist) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %u %d %lld %lld %llu %d %d %d %d\n", std::get<0>(key).c_str(), k.kernel,
-               k.mode, k.nboxes, (long long)k.n_total, (long long)k.cells_total,
-               (unsigned long long)k.shape_hash, c.unroll, c.pipeline, c.span, c.grid_mult);
+  std::fprintf(f, "%s %d %u %d %lld %lld %llu %d %d %d %d %d\n", std::get<0>(key).c_str(),
+               k.kernel, k.mode, k.nboxes, (long long)k.n_total, (long long)k.cells_total,
+               (unsigned long long)k.shape_hash, c.unroll, c.pipeline, c.span, c.grid_mult,
+               c.split);
   std::fclose(f);
 }
 

@@ -1,33 +1,38 @@
 // Adjoint (vector-Jacobian product) of the near-field accelerations.
 //
-// With F(d) = f(r) d (Eq. 3) the Jacobian of one pair is H(d) = f I + h d d^T,
+// With F(d) = f(r) d (Eq. 3, or Eq. 2) the Jacobian of one pair is H(d) = f I + h d d^T,
 // h = f'(r)/r, symmetric and even in d.  For L = sum_i w_i . a_i and the
 // binning held fixed, dL/dx_k = sum_{j in NF(k)} H(d_kj) (w_j - w_k), because
 // the near-field relation is symmetric.  In cell units (d in cell widths):
 //   r >= eps:  f = r^-3,                 h = -3 r^-5
 //   r <  eps:  f = c0 + c1 r + c2 r^2,   h = ha + hb / r   (ha = 12/eps^5, hb = -15/eps^4)
-// and the box-unit gradient is the cell-unit sum times 1/w^3.
+// and for Eq. 2 f = s^-3/2, h = -3 s^-5/2 with s = r^2 + eps_p^2 -- the Newton
+// expressions with eps_p^2 as the guard added to r^2.  The box-unit gradient is
+// the cell-unit sum times 1/w^3.
 //
 // Same traversal and work items as the forward kernel; each source carries
-// (position, cotangent) as two float4s that one wave-uniform 32-byte scalar
-// load brings into SGPRs.
+// (position, cotangent) as a packed 24-byte record that wave-uniform scalar
+// loads bring into SGPRs.
 #include "nf_internal.h"
 
 namespace anf {
 
 __device__ __forceinline__ float rsq_v(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// One adjoint interaction with the source record s = (x, y, z, w_x, w_y, w_z).
 // kNear: the pair may lie inside eps (select between spline and Newton); else
 // every pair of the source cell has r > eps and the Newton branch is exact.
+// Both paths evaluate the Newton branch with the same expressions, so a sink's
+// bits do not depend on which path a work item takes for a source cell.
 template <bool kNear>
-__device__ __forceinline__ void adjoint(const float4 s, const float4 ws, float qx, float qy,
-                                        float qz, float wx, float wy, float wz, float c0, float c1,
-                                        float c2, float ha, float hb, float eps, float& gx,
+__device__ __forceinline__ void adjoint(const float* s, float qx, float qy, float qz, float wx,
+                                        float wy, float wz, float c0, float c1, float c2,
+                                        float ha, float hb, float eps, float g, float& gx,
                                         float& gy, float& gz) {
-  const float dx = s.x - qx;
-  const float dy = s.y - qy;
-  const float dz = s.z - qz;
-  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, kTinyR2)));
+  const float dx = s[0] - qx;
+  const float dy = s[1] - qy;
+  const float dz = s[2] - qz;
+  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, g)));
   const float rinv = rsq_v(r2);
   const float rinv2 = rinv * rinv;
   const float rinv3 = rinv2 * rinv;
@@ -36,25 +41,17 @@ __device__ __forceinline__ void adjoint(const float4 s, const float4 ws, float q
   if (kNear) {
     const float r = r2 * rinv;
     const bool inner = r < eps;
-    f = inner ? __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0) : rinv3;
+    f = inner ? __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0) : f;
     h = inner ? __builtin_fmaf(hb, rinv, ha) : h;
   }
-  const float vx = ws.x - wx;
-  const float vy = ws.y - wy;
-  const float vz = ws.z - wz;
+  const float vx = s[3] - wx;
+  const float vy = s[4] - wy;
+  const float vz = s[5] - wz;
   const float dv = __builtin_fmaf(dz, vz, __builtin_fmaf(dy, vy, dx * vx));
   const float k = h * dv;
   gx = __builtin_fmaf(k, dx, __builtin_fmaf(f, vx, gx));
   gy = __builtin_fmaf(k, dy, __builtin_fmaf(f, vy, gy));
   gz = __builtin_fmaf(k, dz, __builtin_fmaf(f, vz, gz));
-}
-
-__device__ __forceinline__ void two_sum_fold_v(float& a, float& e, float t) {
-  const float s = a + t;
-  const float bp = s - a;
-  const float ap = s - bp;
-  e += (a - ap) + (t - bp);
-  a = s;
 }
 
 __device__ __forceinline__ int wrap1_v(int v, int K) {
@@ -66,74 +63,92 @@ __device__ __forceinline__ int wrap1_v(int v, int K) {
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 struct AdjConst {
-  float c0, c1, c2, ha, hb, eps;
+  float c0, c1, c2, ha, hb, eps, g;
 };
 
+// Sum the sources [beg, end) of packed 24-byte records, kU per step (with kPipe
+// the next kU records are requested before the current ones are used).
 template <int kU, bool kPipe, bool kNear>
-__device__ __forceinline__ void sum_adjoint(const float4* __restrict__ src, int beg, int end,
+__device__ __forceinline__ void sum_adjoint(const float* __restrict__ src6, int beg, int end,
                                             float qx, float qy, float qz, float wx, float wy,
                                             float wz, const AdjConst& k, float& gx, float& gy,
                                             float& gz) {
   int j = beg;
   if (kPipe && j + kU <= end) {
-    float4 cs[kU], cw[kU];
+    float cur[6 * kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) { cs[u] = src[2 * (j + u)]; cw[u] = src[2 * (j + u) + 1]; }
+    for (int u = 0; u < 6 * kU; ++u) cur[u] = src6[6 * j + u];
     for (; j + 2 * kU <= end; j += kU) {
-      float4 ns[kU], nw[kU];
+      float nxt[6 * kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) { ns[u] = src[2 * (j + kU + u)]; nw[u] = src[2 * (j + kU + u) + 1]; }
+      for (int u = 0; u < 6 * kU; ++u) nxt[u] = src6[6 * (j + kU) + u];
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        adjoint<kNear>(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+        adjoint<kNear>(cur + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
+                       gx, gy, gz);
 #pragma unroll
-      for (int u = 0; u < kU; ++u) { cs[u] = ns[u]; cw[u] = nw[u]; }
+      for (int u = 0; u < 6 * kU; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-      adjoint<kNear>(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+      adjoint<kNear>(cur + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, gx,
+                     gy, gz);
     j += kU;
   }
   for (; j + kU <= end; j += kU) {
-    float4 cs[kU], cw[kU];
+    float cur[6 * kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) { cs[u] = src[2 * (j + u)]; cw[u] = src[2 * (j + u) + 1]; }
+    for (int u = 0; u < 6 * kU; ++u) cur[u] = src6[6 * j + u];
 #pragma unroll
     for (int u = 0; u < kU; ++u)
-      adjoint<kNear>(cs[u], cw[u], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, gx, gy, gz);
+      adjoint<kNear>(cur + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, gx,
+                     gy, gz);
   }
-  for (; j < end; ++j)
-    adjoint<kNear>(src[2 * j], src[2 * j + 1], qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb,
-            k.eps, gx, gy, gz);
+  for (; j < end; ++j) {
+    float one[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) one[u] = src6[6 * j + u];
+    adjoint<kNear>(one, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, gx, gy, gz);
+  }
 }
 
-// Interleave (rel_s, w_perm[s]) per sorted slot.
+// Packed source records (rel_s, w_perm[s]) per sorted slot, 6 floats each.
 __global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ rel,
                                                     const int32_t* __restrict__ perm,
                                                     const float* __restrict__ w, int64_t n,
-                                                    float4* __restrict__ src) {
+                                                    float* __restrict__ src6) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int64_t i = perm[s];
-  src[2 * s] = rel[s];
-  src[2 * s + 1] = make_float4(w[3 * i + 0], w[3 * i + 1], w[3 * i + 2], 0.0f);
+  const float4 r = rel[s];
+  src6[6 * s + 0] = r.x;
+  src6[6 * s + 1] = r.y;
+  src6[6 * s + 2] = r.z;
+  src6[6 * s + 3] = w[3 * i + 0];
+  src6[6 * s + 4] = w[3 * i + 1];
+  src6[6 * s + 5] = w[3 * i + 2];
 }
 
 template <int kAcc, int kU, bool kPipe>
 __global__ __launch_bounds__(256) void k_pair_vjp(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
-    const int32_t* __restrict__ queue, const int32_t* __restrict__ n_items_ptr,
-    int32_t* __restrict__ head, const int32_t* __restrict__ off, const float4* __restrict__ src,
-    const int32_t* __restrict__ perm, float* __restrict__ grad) {
+    const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
+    const int32_t* __restrict__ off, const float* __restrict__ src6,
+    const int32_t* __restrict__ perm, float* __restrict__ grad, float* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
-  const int n_items = uni(*n_items_ptr);
+  const int n_tasks = uni(ctrl[kCtrlNTasks]);
+  const int n_whole = uni(ctrl[kCtrlNWhole]);
+  const int n_split = uni(ctrl[kCtrlNSplit]);
+  const int slices = uni(ctrl[kCtrlSlices]);
   while (true) {
     // Every lane takes part in the atomic (lane 0 adds 1, the others 0) so no
     // divergent branch precedes the wave-uniform exit test below.
-    int q = atomicAdd(head, lane == 0 ? 1 : 0);
-    q = uni(__shfl(q, 0, 64));
-    if (q >= n_items) break;
-    const int4 it = items[uni(queue[q])];
+    int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
+    t = uni(__shfl(t, 0, 64));
+    if (t >= n_tasks) break;
+    const int task = uni(tasks[t]);
+    const int code = task & kTaskCodeMask;  // 0: whole item; c > 0: x offset c - 1 - R only
+    const int4 it = items[task >> kTaskShift];
     const int b = uni(it.x & 0xffff), count = uni(it.x >> 16);
     const int cx = uni(it.y & 0xffff), cy = uni(it.y >> 16);
     const int za = uni(it.z & 0xffff), zb = uni(it.z >> 16);
@@ -142,12 +157,14 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
     const int cbase = uni(boxes[b].cell_base);
     AdjConst kc;
     kc.c0 = boxes[b].c0; kc.c1 = boxes[b].c1; kc.c2 = boxes[b].c2;
-    kc.ha = boxes[b].ha; kc.hb = boxes[b].hb; kc.eps = boxes[b].eps;
+    kc.ha = boxes[b].ha; kc.hb = boxes[b].hb; kc.eps = boxes[b].eps; kc.g = boxes[b].guard;
     // c1 and ha each meet another SGPR operand in an FMA; a VALU instruction
     // reads at most one SGPR, so keep them in VGPRs for the whole item.
     asm volatile("" : "+v"(kc.c1), "+v"(kc.ha));
     const int pencil0 = cbase + (cx * K + cy) * K;
-    const bool far_ok = uni(boxes[b].far_newton) != 0;
+    const int far_mode = uni(boxes[b].far_mode);
+    const int ox_lo = code ? code - 1 - R : -R;
+    const int ox_hi = code ? ox_lo : R;
 
     // lane -> sink: the item's sinks are the contiguous slots [first, first+count)
     const int s = lane < count ? first + lane : -1;
@@ -155,19 +172,27 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
     for (int z = za; z < zb; ++z)
       if (s >= uni(off[pencil0 + z + 1])) lane_z = z + 1;
     const bool active = s >= 0;
-    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), wk = make_float4(0.f, 0.f, 0.f, 0.f);
+    float px = 0.f, py = 0.f, pz = 0.f, wkx = 0.f, wky = 0.f, wkz = 0.f;
     if (active) {
-      p = src[2 * s];
-      wk = src[2 * s + 1];
+      px = src6[6 * s + 0];
+      py = src6[6 * s + 1];
+      pz = src6[6 * s + 2];
+      wkx = src6[6 * s + 3];
+      wky = src6[6 * s + 4];
+      wkz = src6[6 * s + 5];
     }
 
+    // (G, E): the sink's sum; (g, e): the current x-offset slice (SINGLE keeps
+    // one running accumulator in g and never folds).
+    float Gx = 0.f, Gy = 0.f, Gz = 0.f, Ex = 0.f, Ey = 0.f, Ez = 0.f;
     float gx = 0.f, gy = 0.f, gz = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
-    for (int ox = -R; ox <= R; ++ox) {
+    for (int ox = ox_lo; ox <= ox_hi; ++ox) {
+      if (kAcc != kAccSingle) gx = gy = gz = ex = ey = ez = 0.f;
       const int sx = wrap1_v(cx + ox, K);
-      const float qx = p.x - (float)ox;
+      const float qx = px - (float)ox;
       for (int oy = -R; oy <= R; ++oy) {
         const int sy = wrap1_v(cy + oy, K);
-        const float qy = p.y - (float)oy;
+        const float qy = py - (float)oy;
         const int col = cbase + (sx * K + sy) * K;
         const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
         for (int zu = za - R; zu <= zb + R; ++zu) {
@@ -175,87 +200,107 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
           const int beg = uni(off[col + sz]), end = uni(off[col + sz + 1]);
           if (beg == end) continue;
           const int oz = zu - lane_z;
-          const bool near = !far_ok || (col_near && zu >= za - 1 && zu <= zb + 1);
+          const bool near = far_mode == kFarNone ||
+                            (far_mode == kFarApart && col_near && zu >= za - 1 && zu <= zb + 1);
           if (active && oz >= -R && oz <= R) {
-            const float qz = p.z - (float)oz;
+            const float qz = pz - (float)oz;
             if (kAcc == kAccSingle) {
               if (near)
-                sum_adjoint<kU, kPipe, true>(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx,
+                sum_adjoint<kU, kPipe, true>(src6, beg, end, qx, qy, qz, wkx, wky, wkz, kc, gx,
                                              gy, gz);
               else
-                sum_adjoint<kU, kPipe, false>(src, beg, end, qx, qy, qz, wk.x, wk.y, wk.z, kc, gx,
+                sum_adjoint<kU, kPipe, false>(src6, beg, end, qx, qy, qz, wkx, wky, wkz, kc, gx,
                                               gy, gz);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
                 if (near)
-                  sum_adjoint<kU, kPipe, true>(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx,
+                  sum_adjoint<kU, kPipe, true>(src6, cb, ce, qx, qy, qz, wkx, wky, wkz, kc, tx,
                                                ty, tz);
                 else
-                  sum_adjoint<kU, kPipe, false>(src, cb, ce, qx, qy, qz, wk.x, wk.y, wk.z, kc, tx,
+                  sum_adjoint<kU, kPipe, false>(src6, cb, ce, qx, qy, qz, wkx, wky, wkz, kc, tx,
                                                 ty, tz);
                 if (kAcc == kAccChunked) {
                   gx += tx; gy += ty; gz += tz;
                 } else {
-                  two_sum_fold_v(gx, ex, tx);
-                  two_sum_fold_v(gy, ey, ty);
-                  two_sum_fold_v(gz, ez, tz);
+                  two_sum_fold(gx, ex, tx);
+                  two_sum_fold(gy, ey, ty);
+                  two_sum_fold(gz, ez, tz);
                 }
               }
             }
           }
         }
       }
+      if (kAcc != kAccSingle && code == 0) {
+        slice_fold<kAcc>(Gx, Ex, gx, ex);
+        slice_fold<kAcc>(Gy, Ey, gy, ey);
+        slice_fold<kAcc>(Gz, Ez, gz, ez);
+      }
     }
-    if (active) {
-      const float iw3 = boxes[b].inv_w3;
-      const int64_t i = perm[s];
-      grad[3 * i + 0] = (gx + ex) * iw3;
-      grad[3 * i + 1] = (gy + ey) * iw3;
-      grad[3 * i + 2] = (gz + ez) * iw3;
+    if (kAcc == kAccSingle) {
+      Gx = gx; Gy = gy; Gz = gz;
+    }
+    if (code == 0) {
+      if (active) {
+        const float iw3 = boxes[b].inv_w3;
+        const int64_t i = perm[s];
+        grad[3 * i + 0] = (Gx + Ex) * iw3;
+        grad[3 * i + 1] = (Gy + Ey) * iw3;
+        grad[3 * i + 2] = (Gz + Ez) * iw3;
+      }
+    } else {
+      // a tail item split by x offset: keep this slice for k_combine_slices
+      const int slot = (t - n_whole) % n_split;
+      float* dst = partial + (int64_t)(slot * slices + (code - 1)) * kPartialStride * kTile + lane;
+      dst[0 * kTile] = gx; dst[1 * kTile] = gy; dst[2 * kTile] = gz;
+      dst[3 * kTile] = ex; dst[4 * kTile] = ey; dst[5 * kTile] = ez;
     }
   }
 }
 
 template <int kAcc, int kU, bool kPipe>
-static hipError_t launch_vjp_t(const DevBox* boxes, const PlanWork& w, int64_t pencils,
-                               const int32_t* off, const float4* src, const int32_t* perm,
-                               float* grad, int grid_mult, hipStream_t s) {
+static hipError_t launch_vjp_t(const DevBox* boxes, const PlanWork& w, const int32_t* off,
+                               const float* src, const int32_t* perm, float* grad, int grid_mult,
+                               hipStream_t s) {
   const void* fn = reinterpret_cast<const void*>(&k_pair_vjp<kAcc, kU, kPipe>);
   const int blocks = persistent_blocks(fn, 256) * grid_mult;
   hipLaunchKernelGGL((k_pair_vjp<kAcc, kU, kPipe>), dim3(blocks), dim3(256), 0, s, boxes, w.items,
-                     w.queue, w.item_base + pencils, plan_head(w), off, src, perm, grad);
+                     w.tasks, w.ctrl, off, src, perm, grad, w.partial);
   return hipGetLastError();
 }
 
 template <int kAcc>
 static hipError_t dispatch_vjp(const KernelConfig& cfg, const DevBox* boxes, const PlanWork& w,
-                               int64_t pencils, const int32_t* off, const float4* src,
-                               const int32_t* perm, float* grad, hipStream_t s) {
+                               const int32_t* off, const float* src, const int32_t* perm,
+                               float* grad, hipStream_t s) {
   const int g = cfg.grid_mult;
   switch (cfg.unroll * 2 + (cfg.pipeline ? 1 : 0)) {
-    case 5: return launch_vjp_t<kAcc, 2, true>(boxes, w, pencils, off, src, perm, grad, g, s);
-    case 8: return launch_vjp_t<kAcc, 4, false>(boxes, w, pencils, off, src, perm, grad, g, s);
-    case 9: return launch_vjp_t<kAcc, 4, true>(boxes, w, pencils, off, src, perm, grad, g, s);
-    default: return launch_vjp_t<kAcc, 2, false>(boxes, w, pencils, off, src, perm, grad, g, s);
+    case 5: return launch_vjp_t<kAcc, 2, true>(boxes, w, off, src, perm, grad, g, s);
+    case 8: return launch_vjp_t<kAcc, 4, false>(boxes, w, off, src, perm, grad, g, s);
+    case 9: return launch_vjp_t<kAcc, 4, true>(boxes, w, off, src, perm, grad, g, s);
+    default: return launch_vjp_t<kAcc, 2, false>(boxes, w, off, src, perm, grad, g, s);
   }
 }
 
 hipError_t launch_vjp(AccMode mode, const KernelConfig& cfg, const DevBox* boxes,
                       const PlanWork& w, int64_t pencils, const int32_t* off, const float* rel,
-                      const int32_t* perm, const float* wvec, float4* src_w, int64_t n_total,
+                      const int32_t* perm, const float* wvec, float* src_w, int64_t n_total,
                       float* grad, hipStream_t s) {
+  (void)pencils;
   if (n_total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_src, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(rel), perm, wvec, n_total, src_w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (mode) {
-    case kAccSingle: return dispatch_vjp<kAccSingle>(cfg, boxes, w, pencils, off, src_w, perm, grad, s);
-    case kAccChunked: return dispatch_vjp<kAccChunked>(cfg, boxes, w, pencils, off, src_w, perm, grad, s);
-    default: return dispatch_vjp<kAccCompensated>(cfg, boxes, w, pencils, off, src_w, perm, grad, s);
+    case kAccSingle: e = dispatch_vjp<kAccSingle>(cfg, boxes, w, off, src_w, perm, grad, s); break;
+    case kAccChunked: e = dispatch_vjp<kAccChunked>(cfg, boxes, w, off, src_w, perm, grad, s); break;
+    default: e = dispatch_vjp<kAccCompensated>(cfg, boxes, w, off, src_w, perm, grad, s); break;
   }
+  if (e != hipSuccess) return e;
+  return launch_combine(mode, true, boxes, w, perm, grad, nullptr, s);
 }
 
 }  // namespace anf

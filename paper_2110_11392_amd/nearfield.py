@@ -25,19 +25,23 @@ from . import _lib
 @dataclasses.dataclass(frozen=True)
 class BoxSpec:
     """One periodic box: n particles, side ``box``, ``cpd`` cells per dimension,
-    near-field radius ``radius`` (cells) and Plummer-equivalent softening."""
+    near-field radius ``radius`` (cells), Plummer-equivalent softening and the
+    optional top-hat radius of the density estimate (0: none)."""
     n: int
     box: float
     cpd: int
     radius: int
     eps_plummer: float
+    density_radius: float = 0.0
 
     def astuple(self):
-        return (self.n, self.box, self.cpd, self.radius, self.eps_plummer)
+        return (self.n, self.box, self.cpd, self.radius, self.eps_plummer, self.density_radius)
 
 
 ACCUMULATION = {"compensated": _lib.COMPENSATED, "chunked": _lib.CHUNKED,
                 "single": _lib.SINGLE_ACC}
+# Force laws: the spline of Eq. 3 (eps_s = 2.16 eps_p) or Plummer's Eq. 2.
+LAWS = {"spline": 0, "plummer": _lib.PLUMMER}
 
 
 @dataclasses.dataclass
@@ -68,9 +72,13 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 class NearField:
-    """Resolved box list plus a reusable device workspace."""
+    """Resolved box list plus a reusable device workspace; ``law`` selects the
+    force law of every call ("spline", Eq. 3, or "plummer", Eq. 2)."""
 
-    def __init__(self, boxes: Sequence[BoxSpec], device=None):
+    def __init__(self, boxes: Sequence[BoxSpec], device=None, law: str = "spline"):
+        if law not in LAWS:
+            raise ValueError(f"unknown force law {law!r}")
+        self.law = law
         lib = _lib.load()
         self.specs: List[BoxSpec] = list(boxes)
         self._boxes = _lib.box_array([b.astuple() for b in self.specs])
@@ -90,6 +98,11 @@ class NearField:
         self._lib = lib
 
     # -- helpers -----------------------------------------------------------
+    def _flags(self, accumulation: str) -> int:
+        if accumulation not in ACCUMULATION:
+            raise ValueError(f"unknown accumulation {accumulation!r}")
+        return ACCUMULATION[accumulation] | LAWS[self.law]
+
     def _check_pos(self, pos: torch.Tensor):
         if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
             raise ValueError("positions must be an (n, 3) float32 tensor")
@@ -120,11 +133,19 @@ class NearField:
     def forces(self, binned: Binned, accumulation: str = "compensated",
                out: Optional[torch.Tensor] = None, momentum: bool = False,
                count_pairs: bool = False, momentum_out: Optional[torch.Tensor] = None,
-               pairs_out: Optional[torch.Tensor] = None
+               pairs_out: Optional[torch.Tensor] = None,
+               density_out: Optional[torch.Tensor] = None
                ) -> Tuple[torch.Tensor, Optional[torch.Tensor], Optional[torch.Tensor]]:
         """Accelerations (n, 3) in original order; optionally the per-box FP64
-        momentum sums (nboxes, 4) and the evaluated pair count (1,) int64."""
-        flags = ACCUMULATION[accumulation] | (_lib.COUNT_PAIRS if count_pairs else 0)
+        momentum sums (nboxes, 4) and the evaluated pair count (1,) int64.  With
+        ``density_out`` (a contiguous (n,) float32 tensor; every box needs a
+        density radius) the same pass also writes the top-hat density estimate."""
+        if density_out is not None and (density_out.dtype != torch.float32
+                                        or tuple(density_out.shape) != (self.n_total,)
+                                        or not density_out.is_contiguous()
+                                        or density_out.device != self.device):
+            raise ValueError("density_out must be a contiguous (n,) float32 tensor")
+        flags = self._flags(accumulation) | (_lib.COUNT_PAIRS if count_pairs else 0)
         acc = out if out is not None else torch.empty((self.n_total, 3), dtype=torch.float32,
                                                       device=self.device)
         mom = momentum_out
@@ -135,8 +156,9 @@ class NearField:
             pairs = torch.empty(1, dtype=torch.int64, device=self.device)
         cs = binned.cstruct()
         _lib.check(self._lib.abacus_nf_forces(self._boxes, self.nboxes, ctypes.byref(cs), _ptr(acc),
-                                              _ptr(mom), _ptr(pairs), flags, _ptr(self.workspace),
-                                              self.workspace_bytes, _stream()),
+                                              _ptr(density_out), _ptr(mom), _ptr(pairs), flags,
+                                              _ptr(self.workspace), self.workspace_bytes,
+                                              _stream()),
                    "abacus_nf_forces")
         return acc, mom, pairs
 
@@ -148,12 +170,79 @@ class NearField:
                                                        device=self.device)
         cs = binned.cstruct()
         _lib.check(self._lib.abacus_nf_forces_vjp(self._boxes, self.nboxes, ctypes.byref(cs),
-                                                  _ptr(w), _ptr(grad), ACCUMULATION[accumulation],
+                                                  _ptr(w), _ptr(grad), self._flags(accumulation),
                                                   _ptr(self.workspace), self.workspace_bytes,
                                                   _stream()),
                    "abacus_nf_forces_vjp")
         return grad
 
+
+    def multipoles(self, binned: Binned, order: int, reduced: bool = False,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Cell multipoles of Eq. 4 about every cell centre, (cells_total, terms)
+        FP64 in box units: the complete basis of ``order`` or its (p+1)^2
+        reduction (see include/abacus_nf.h)."""
+        flags = _lib.REDUCED if reduced else 0
+        terms = ctypes.c_int64(0)
+        _lib.check(self._lib.abacus_nf_multipole_terms(int(order), flags, ctypes.byref(terms)),
+                   "abacus_nf_multipole_terms")
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(self._lib.abacus_nf_multipoles_workspace_bytes(
+            self._boxes, self.nboxes, int(order), flags, ctypes.byref(nbytes)),
+            "abacus_nf_multipoles_workspace_bytes")
+        if getattr(self, "_mp_ws", None) is None or self._mp_ws.numel() < nbytes.value:
+            self._mp_ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8,
+                                      device=self.device)
+        shape = (self.cells_total, int(terms.value))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=self.device)
+        elif out.dtype != torch.float64 or tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {shape} float64 tensor")
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_multipoles(self._boxes, self.nboxes, ctypes.byref(cs),
+                                                  int(order), flags, _ptr(out), _ptr(self._mp_ws),
+                                                  self._mp_ws.numel(), _stream()),
+                   "abacus_nf_multipoles")
+        return out
+
+    def kick_drift(self, binned: Binned, pos: torch.Tensor, vel: torch.Tensor,
+                   acc: torch.Tensor, kick, drift, cell_stats: bool = False,
+                   box_stats: bool = True) -> Tuple[Optional[torch.Tensor], Optional[torch.Tensor]]:
+        """One leapfrog kick and drift of ``vel`` and ``pos`` in place (``binned``
+        must be the binning of ``pos`` before the call); returns the optional
+        per-cell (v_rms, a_max) and per-box (min_c v_rms/a_max, v_rms, a_max, N)
+        FP64 statistics of Eq. 1.  ``kick`` / ``drift``: one factor for every box
+        or a sequence of nboxes factors."""
+        self._check_pos(pos)
+        for name, t in (("vel", vel), ("acc", acc)):
+            if t.dtype != torch.float32 or tuple(t.shape) != (self.n_total, 3) or \
+                    not t.is_contiguous() or t.device != self.device:
+                raise ValueError(f"{name} must be a contiguous (n, 3) float32 tensor")
+        k = [float(kick)] * self.nboxes if not hasattr(kick, "__len__") else [float(x) for x in kick]
+        d = [float(drift)] * self.nboxes if not hasattr(drift, "__len__") else [float(x) for x in drift]
+        if len(k) != self.nboxes or len(d) != self.nboxes:
+            raise ValueError("kick and drift need one factor per box")
+        karr = (ctypes.c_double * self.nboxes)(*k)
+        darr = (ctypes.c_double * self.nboxes)(*d)
+        cs = torch.empty((self.cells_total, 2), dtype=torch.float64, device=self.device) \
+            if cell_stats else None
+        bs = torch.empty((self.nboxes, 4), dtype=torch.float64, device=self.device) \
+            if box_stats else None
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(self._lib.abacus_nf_kick_drift_workspace_bytes(self._boxes, self.nboxes,
+                                                                  ctypes.byref(nbytes)),
+                   "abacus_nf_kick_drift_workspace_bytes")
+        ws = self.workspace
+        if nbytes.value > ws.numel():
+            if getattr(self, "_kdk_ws", None) is None or self._kdk_ws.numel() < nbytes.value:
+                self._kdk_ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            ws = self._kdk_ws
+        b = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_kick_drift(self._boxes, self.nboxes, ctypes.byref(b), karr,
+                                                  darr, _ptr(pos), _ptr(vel), _ptr(acc), _ptr(cs),
+                                                  _ptr(bs), _ptr(ws), ws.numel(), _stream()),
+                   "abacus_nf_kick_drift")
+        return cs, bs
 
     # -- tuning ------------------------------------------------------------------
     def autotune(self, binned: Binned, accumulation: str = "compensated") -> dict:
@@ -163,7 +252,7 @@ class NearField:
         fwd, adj = _lib.Tuning(), _lib.Tuning()
         cs = binned.cstruct()
         _lib.check(self._lib.abacus_nf_autotune(self._boxes, self.nboxes, ctypes.byref(cs),
-                                                _ptr(scratch), ACCUMULATION[accumulation],
+                                                _ptr(scratch), self._flags(accumulation),
                                                 _ptr(self.workspace), self.workspace_bytes,
                                                 _stream(), ctypes.byref(fwd), ctypes.byref(adj)),
                    "abacus_nf_autotune")
@@ -172,7 +261,7 @@ class NearField:
     def get_tuning(self, kernel: int, accumulation: str = "compensated") -> dict:
         t = _lib.Tuning()
         _lib.check(self._lib.abacus_nf_get_tuning(self._boxes, self.nboxes,
-                                                  ACCUMULATION[accumulation], kernel,
+                                                  self._flags(accumulation), kernel,
                                                   ctypes.byref(t)), "abacus_nf_get_tuning")
         return t.asdict()
 
@@ -180,7 +269,7 @@ class NearField:
                    accumulation: str = "compensated") -> None:
         t = None if tuning is None else ctypes.byref(_lib.Tuning(**tuning))
         _lib.check(self._lib.abacus_nf_set_tuning(self._boxes, self.nboxes,
-                                                  ACCUMULATION[accumulation], kernel, t),
+                                                  self._flags(accumulation), kernel, t),
                    "abacus_nf_set_tuning")
 
 
@@ -205,11 +294,20 @@ class _NearFieldFn(torch.autograd.Function):
 
 
 def near_field(pos: torch.Tensor, box: float, cpd: int, radius: int, eps_plummer: float,
-               compensated: bool = True, nf: Optional[NearField] = None) -> torch.Tensor:
+               compensated: bool = True, nf: Optional[NearField] = None,
+               law: str = "spline") -> torch.Tensor:
     """Near-field accelerations of one periodic box, differentiable in ``pos``."""
     if nf is None:
-        nf = NearField([BoxSpec(pos.shape[0], box, cpd, radius, eps_plummer)], device=pos.device)
+        nf = NearField([BoxSpec(pos.shape[0], box, cpd, radius, eps_plummer)], device=pos.device,
+                       law=law)
     return _NearFieldFn.apply(pos, nf, "compensated" if compensated else "chunked")
+
+
+def timestep(box_stats, a: float, H: float, eta_acc: float, eta_H: float) -> float:
+    """Eq. 1 for one box from its four kick-drift statistics (host arithmetic)."""
+    arr = (ctypes.c_double * 4)(*[float(x) for x in box_stats])
+    return float(_lib.load().abacus_nf_timestep(arr, float(a), float(H), float(eta_acc),
+                                                float(eta_H)))
 
 
 def timing_enable(enable: bool = True) -> None:

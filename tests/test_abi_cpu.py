@@ -52,6 +52,11 @@ def boxes(*specs):
     ((100, 1.0, 8, 2, 0.0), _lib.EINVAL),
     ((100, 1.0, 8, 2, float("nan")), _lib.EINVAL),
     ((100, 1.0, 8, 2, 1e-12), _lib.EINVAL),          # softening below 1e-6 cells
+    ((100, 1.0, 8, 2, 1e-3, 0.25), _lib.OK),         # density radius = R cells
+    ((100, 1.0, 8, 2, 1e-3, 0.2501), _lib.EINVAL),   # density radius beyond R cells
+    ((100, 1.0, 8, 2, 1e-3, -0.1), _lib.EINVAL),
+    ((100, 1.0, 8, 2, 1e-3, float("nan")), _lib.EINVAL),
+    ((100, 1.0, 8, 2, 1e-3, 1e-20), _lib.EINVAL),    # b^2 below 1e-30 cells^2
     ((2 ** 31, 1.0, 8, 2, 1e-3), _lib.ERANGE),
     ((100, 1.0, 1300, 2, 1e-3), _lib.ERANGE),        # K^3 >= 2^31
 ])
@@ -95,15 +100,21 @@ def test_entry_points_validate_before_device_work():
     assert lib.abacus_nf_bin(b, 1, fake, ctypes.byref(binned), fake, nbytes.value - 1, None) == \
         _lib.EWORKSPACE
     # forces: bad flags, conflicting accumulation modes, missing pair counter
-    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, 0x100, fake, nbytes,
-                                None) == _lib.EINVAL
-    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None,
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, None, 0x100, fake,
+                                nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, None,
                                 _lib.SINGLE_ACC | _lib.COMPENSATED, fake, nbytes, None) == \
         _lib.EINVAL
-    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, _lib.COUNT_PAIRS,
-                                fake, nbytes, None) == _lib.EINVAL
-    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), None, None, None, 0, fake, nbytes,
-                                None) == _lib.EINVAL
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, None, None, None,
+                                _lib.COUNT_PAIRS, fake, nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), None, None, None, None, 0, fake,
+                                nbytes, None) == _lib.EINVAL
+    # density: the box needs a radius, and pair counting excludes it
+    assert lib.abacus_nf_forces(b, 1, ctypes.byref(binned), fake, fake, None, None, 0, fake,
+                                nbytes, None) == _lib.EINVAL
+    bd = boxes((100, 1.0, 8, 2, 1e-3, 0.1))
+    assert lib.abacus_nf_forces(bd, 1, ctypes.byref(binned), fake, fake, None, fake,
+                                _lib.COUNT_PAIRS, fake, nbytes, None) == _lib.EINVAL
     # adjoint: no pair counting, null cotangent
     assert lib.abacus_nf_forces_vjp(b, 1, ctypes.byref(binned), fake, fake, _lib.COUNT_PAIRS, fake,
                                     nbytes, None) == _lib.EINVAL
@@ -122,7 +133,7 @@ def test_timing_hooks_without_gpu():
     ms, n = ctypes.c_double(1.0), ctypes.c_int64(5)
     assert lib.abacus_nf_timing_read(0, ctypes.byref(ms), ctypes.byref(n)) == 0
     assert ms.value == 0.0 and n.value == 0
-    assert lib.abacus_nf_timing_read(7, None, None) == _lib.EINVAL
+    assert lib.abacus_nf_timing_read(6, None, None) == _lib.EINVAL
 
 
 def test_tuning_registry_validation():
@@ -131,25 +142,25 @@ def test_tuning_registry_validation():
     b = boxes((5000, 1.0, 16, 2, 1e-3))
     t = _lib.Tuning()
     assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
-    assert (t.unroll, t.pipeline, t.span, t.grid_mult) == (4, 0, 2, 1)
+    assert (t.unroll, t.pipeline, t.span, t.grid_mult, t.split) == (4, 0, 2, 1, 1)
     assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_ADJOINT, ctypes.byref(t)) == 0
     assert (t.unroll, t.span) == (2, 2)
-    new = _lib.Tuning(8, 1, 3, 2)
+    new = _lib.Tuning(8, 1, 3, 2, 0)
     assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(new)) == 0
     assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
-    assert t.asdict() == {"unroll": 8, "pipeline": 1, "span": 3, "grid_mult": 2}
+    assert t.asdict() == {"unroll": 8, "pipeline": 1, "span": 3, "grid_mult": 2, "split": 0}
     # other accumulation mode is a different key
     assert lib.abacus_nf_get_tuning(b, 1, _lib.CHUNKED, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
     assert t.unroll == 4
     assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD, None) == 0
     assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
     assert t.unroll == 4
-    for bad in (_lib.Tuning(3, 0, 2, 1), _lib.Tuning(4, 2, 2, 1), _lib.Tuning(4, 0, 0, 1),
-                _lib.Tuning(4, 0, 4, 1), _lib.Tuning(4, 0, 2, 3)):
+    for bad in (_lib.Tuning(3, 0, 2, 1, 1), _lib.Tuning(4, 2, 2, 1, 1), _lib.Tuning(4, 0, 0, 1, 1),
+                _lib.Tuning(4, 0, 4, 1, 1), _lib.Tuning(4, 0, 2, 3, 1), _lib.Tuning(4, 0, 2, 1, 2)):
         assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(bad)) == \
             _lib.EINVAL
     assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_ADJOINT,
-                                    ctypes.byref(_lib.Tuning(8, 0, 2, 1))) == _lib.EINVAL
+                                    ctypes.byref(_lib.Tuning(8, 0, 2, 1, 1))) == _lib.EINVAL
     assert lib.abacus_nf_set_tuning(b, 1, 0, 2, None) == _lib.EINVAL
     assert lib.abacus_nf_get_tuning(b, 1, 0, 0, None) == _lib.EINVAL
 
@@ -167,3 +178,79 @@ def test_autotune_validates_before_device_work():
                                   nbytes, None, None, None) == _lib.EINVAL
     assert lib.abacus_nf_autotune(b, 1, ctypes.byref(binned), fake, 0, fake, 16, None, None,
                                   None) == _lib.EWORKSPACE
+
+
+def test_force_laws_keep_separate_tunings():
+    """The Plummer flag is accepted and keys its own launch shapes (host-only)."""
+    lib = _lib.load()
+    b = boxes((7000, 1.0, 16, 2, 1e-3))
+    t = _lib.Tuning()
+    assert lib.abacus_nf_set_tuning(b, 1, 0, _lib.KERNEL_FORWARD,
+                                    ctypes.byref(_lib.Tuning(2, 1, 1, 1, 0))) == 0
+    assert lib.abacus_nf_get_tuning(b, 1, _lib.PLUMMER, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert (t.unroll, t.pipeline, t.span, t.grid_mult, t.split) == (4, 0, 2, 1, 1)
+    assert lib.abacus_nf_set_tuning(b, 1, _lib.PLUMMER, _lib.KERNEL_FORWARD,
+                                    ctypes.byref(_lib.Tuning(8, 0, 3, 1, 1))) == 0
+    assert lib.abacus_nf_get_tuning(b, 1, 0, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert (t.unroll, t.pipeline, t.span) == (2, 1, 1)
+    assert lib.abacus_nf_get_tuning(b, 1, _lib.PLUMMER, _lib.KERNEL_FORWARD, ctypes.byref(t)) == 0
+    assert (t.unroll, t.span) == (8, 3)
+    assert lib.abacus_nf_get_tuning(b, 1, 0x40, _lib.KERNEL_FORWARD, ctypes.byref(t)) == \
+        _lib.EINVAL
+    for flags in (0, _lib.PLUMMER):
+        assert lib.abacus_nf_set_tuning(b, 1, flags, _lib.KERNEL_FORWARD, None) == 0
+
+
+def test_multipole_arguments_without_gpu():
+    lib = _lib.load()
+    t = ctypes.c_int64(0)
+    for p in range(0, 9):
+        assert lib.abacus_nf_multipole_terms(p, 0, ctypes.byref(t)) == 0
+        assert t.value == (p + 3) * (p + 2) * (p + 1) // 6
+        assert lib.abacus_nf_multipole_terms(p, _lib.REDUCED, ctypes.byref(t)) == 0
+        assert t.value == (p + 1) ** 2
+    assert lib.abacus_nf_multipole_terms(9, 0, ctypes.byref(t)) == _lib.EINVAL
+    assert lib.abacus_nf_multipole_terms(-1, 0, ctypes.byref(t)) == _lib.EINVAL
+    assert lib.abacus_nf_multipole_terms(4, 0x1, ctypes.byref(t)) == _lib.EINVAL
+    b = boxes((1000, 1.0, 8, 2, 1e-3))
+    small, big = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.abacus_nf_multipoles_workspace_bytes(b, 1, 8, 0, ctypes.byref(small)) == 0
+    assert lib.abacus_nf_multipoles_workspace_bytes(b, 1, 8, _lib.REDUCED, ctypes.byref(big)) == 0
+    assert big.value >= small.value + 8 * 165 * 8 ** 3
+    fake = ctypes.c_void_p(0x1000)
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    assert lib.abacus_nf_multipoles(b, 1, ctypes.byref(binned), 8, 0, None, fake, small,
+                                    None) == _lib.EINVAL
+    assert lib.abacus_nf_multipoles(b, 1, ctypes.byref(binned), 8, 0, fake, fake,
+                                    small.value - 1, None) == _lib.EWORKSPACE
+    assert lib.abacus_nf_multipoles(b, 1, ctypes.byref(binned), 9, 0, fake, fake, small,
+                                    None) == _lib.EINVAL
+
+
+def test_kick_drift_arguments_without_gpu():
+    lib = _lib.load()
+    b = boxes((100, 1.0, 8, 2, 1e-3))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.abacus_nf_kick_drift_workspace_bytes(b, 1, ctypes.byref(nbytes)) == 0
+    assert nbytes.value >= 16 * 8 ** 3
+    fake = ctypes.c_void_p(0x1000)
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    one = (ctypes.c_double * 1)(0.1)
+    bad = (ctypes.c_double * 1)(float("inf"))
+    args = (fake, fake, fake, None, None, fake, nbytes, None)
+    assert lib.abacus_nf_kick_drift(b, 1, ctypes.byref(binned), None, one, *args) == _lib.EINVAL
+    assert lib.abacus_nf_kick_drift(b, 1, ctypes.byref(binned), one, bad, *args) == _lib.EINVAL
+    assert lib.abacus_nf_kick_drift(b, 1, ctypes.byref(binned), one, one, None, fake, fake, None,
+                                    None, fake, nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_kick_drift(b, 1, ctypes.byref(binned), one, one, fake, fake, fake, None,
+                                    None, fake, nbytes.value - 1, None) == _lib.EWORKSPACE
+
+
+def test_timestep_matches_oracle_on_host():
+    import oracle
+    for stats in ([10.0, 1.0, 1.0, 100], [0.02, 1.0, 100.0, 100], [1e-6, 1.0, 10.0, 100],
+                  [float("inf"), 1.0, 0.0, 100]):
+        for eta_h in (0.03, 0.1):
+            arr = (ctypes.c_double * 4)(*stats)
+            got = _lib.load().abacus_nf_timestep(arr, 0.5, 2.0, 0.25, eta_h)
+            assert got == oracle.timestep(stats, 0.5, 2.0, 0.25, eta_h)

@@ -1,0 +1,113 @@
+"""GPU parity of the kick-drift step with the Eq. 1 statistics.
+
+Each particle update is the same FP64 multiply-then-add rounded once to FP32 on
+both sides, and the wrap is the same FP64 floor arithmetic, so positions and
+velocities must match the oracle bit for bit.  The per-cell maximum |a| is a
+maximum of identically computed values (exact).  Sums of |v|^2 are formed in
+a different order (the oracle adds one particle after another); n positive
+terms summed in any order differ from the exact sum by at most (n - 1) u of it
+(u = 2^-53), so the rms values agree within n 2^-52 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_11392_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def anf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_11392_amd as m
+    return m
+
+
+def state(boxes, seed):
+    n = sum(b.n for b in boxes)
+    vel = synth.gaussian_weights(n, seed) * np.float32(0.05)
+    acc = synth.gaussian_weights(n, seed + 1) * np.float32(4.0)
+    return vel, acc
+
+
+def run_case(anf, boxes, kick, drift, seed=400):
+    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer) for b in boxes])
+    pos_h = np.ascontiguousarray(np.concatenate([b.pos for b in boxes]))
+    vel_h, acc_h = state(boxes, seed)
+    pos = torch.from_numpy(pos_h).cuda()
+    vel = torch.from_numpy(vel_h).cuda()
+    acc = torch.from_numpy(acc_h).cuda()
+    bd = nf.bin(pos)
+    cs, bs = nf.kick_drift(bd, pos, vel, acc, kick, drift, cell_stats=True)
+    got = (pos.cpu().numpy(), vel.cpu().numpy(), cs.cpu().numpy(), bs.cpu().numpy())
+    first, cell0 = 0, 0
+    ks = kick if hasattr(kick, "__len__") else [kick] * len(boxes)
+    ds = drift if hasattr(drift, "__len__") else [drift] * len(boxes)
+    for k, b in enumerate(boxes):
+        sl = slice(first, first + b.n)
+        po, vo, cso, bso = oracle.kick_drift(b.pos, vel_h[sl], acc_h[sl], b.box, b.cpd, ks[k],
+                                             ds[k])
+        assert np.array_equal(got[0][sl].view(np.uint32), po.view(np.uint32)), k
+        assert np.array_equal(got[1][sl].view(np.uint32), vo.view(np.uint32)), k
+        ncell = b.cpd ** 3
+        cg = got[2][cell0:cell0 + ncell]
+        _, offs, _, _ = oracle.bin(b.pos, b.box, b.cpd)
+        nc = np.maximum(np.diff(offs), 1).astype(np.float64)
+        assert np.all(np.abs(cg[:, 0] - cso[:, 0]) <= nc * 2.0 ** -52 * cso[:, 0]), k
+        assert np.array_equal(cg[:, 1], cso[:, 1]), k
+        bg = got[3][k]
+        rtol = max(b.n, 1) * 2.0 ** -52
+        if np.isinf(bso[0]):
+            assert np.isinf(bg[0])
+        else:
+            # the ratio of one cell: that cell's sum bound, at most the box's
+            assert bg[0] == pytest.approx(bso[0], rel=rtol)
+        assert bg[1] == pytest.approx(bso[1], rel=rtol, abs=0)
+        assert bg[2] == bso[2] and bg[3] == bso[3]
+        first += b.n
+        cell0 += ncell
+    return nf, got
+
+
+def test_kdk_c1(anf):
+    say("[kdk] C1")
+    run_case(anf, synth.config("C1"), 0.01, 0.02)
+
+
+def test_kdk_wraps_and_big_steps(anf):
+    say("[kdk] clustered K9, drift of several boxes")
+    boxes = [synth.Box(synth.clustered(5000, 12, 9, 10), 1.0, 9, 1, 1 / 700)]
+    run_case(anf, boxes, 0.5, 41.0)
+
+
+def test_kdk_ragged_batch_with_per_box_factors(anf):
+    boxes = [synth.Box(synth.clustered(2500, 6, 8, 13), 1.0, 8, 2, 1 / 500),
+             synth.Box(np.zeros((0, 3), np.float32), 1.0, 5, 2, 1 / 500),
+             synth.Box(synth.uniform(1, 14), 2.0, 5, 2, 1 / 500),
+             synth.Box(synth.clustered(4100, 9, 70, 15), 1.0, 70, 2, 1 / 700),
+             synth.Box(synth.uniform(3000, 16, 3.7), 3.7, 11, 2, 3.7 / 640)]
+    say("[kdk] ragged batch")
+    run_case(anf, boxes, [0.01, 0.02, -0.03, 0.5, 0.0], [0.02, 0.0, 1.5, -0.25, 0.125])
+
+
+def test_kdk_c2_deterministic_and_timestep(anf):
+    boxes = synth.config("C2")
+    say(f"[kdk] C2 n={boxes[0].n}")
+    nf, got = run_case(anf, boxes, 0.003, 0.001)
+    # same inputs again: identical bits, including the statistics
+    _, again = run_case(anf, boxes, 0.003, 0.001)
+    for x, y in zip(got, again):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    bs = got[3][0]
+    assert anf.timestep(bs, 0.5, 1.2, 0.25, 0.03) == pytest.approx(
+        oracle.timestep(bs, 0.5, 1.2, 0.25, 0.03), rel=1e-15)

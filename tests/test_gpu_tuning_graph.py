@@ -35,12 +35,14 @@ def bits(t):
     return t.detach().cpu().numpy().view(np.uint32)
 
 
-FORWARD_SHAPES = [dict(unroll=u, pipeline=p, span=s, grid_mult=g)
+FORWARD_SHAPES = [dict(unroll=u, pipeline=p, span=s, grid_mult=g, split=x)
                   for u in (2, 4, 8) for p in (0, 1) for s in (1, 2, 3) for g in (1, 2)
-                  if (s == 2 or (u == 4 and p == 0)) and (g == 1 or (u == 4 and s == 2))]
-ADJOINT_SHAPES = [dict(unroll=u, pipeline=p, span=s, grid_mult=1)
-                  for u in (2, 4) for p in (0, 1) for s in (1, 2, 3)
-                  if s == 2 or (u == 2 and p == 0)]
+                  for x in (0, 1)
+                  if (s == 2 or (u == 4 and p == 0)) and (g == 1 or (u == 4 and s == 2))
+                  and (x == 1 or (u == 4 and g == 1))]
+ADJOINT_SHAPES = [dict(unroll=u, pipeline=p, span=s, grid_mult=1, split=x)
+                  for u in (2, 4) for p in (0, 1) for s in (1, 2, 3) for x in (0, 1)
+                  if (s == 2 or (u == 2 and p == 0)) and (x == 1 or (u == 2 and p == 0))]
 
 
 def test_every_launch_shape_is_bit_identical(anf):

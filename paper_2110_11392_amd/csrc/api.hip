@@ -590,8 +590,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
 // ---- cell multipoles ---------------------------------------------------------
 
 struct MpLayout {
-  size_t boxtab, wave_count, wave_base, scan, waves, full, total;
-  int64_t max_waves;
+  size_t boxtab, keys, hist, base, cursor, waves, sorted, full, total;
 };
 
 MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
@@ -603,12 +602,12 @@ MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
     return at;
   };
   L.boxtab = take(sizeof(DevBox) * r.boxes.size());
-  L.wave_count = take(4 * (size_t)r.pencils_total);
-  L.wave_base = take(4 * (size_t)(r.pencils_total + 1));
-  L.scan = take(4 * (size_t)scan_tmp_ints(r.pencils_total));
-  // every wave holds at least one cell
-  L.max_waves = r.cells_total;
-  L.waves = take(sizeof(int4) * (size_t)L.max_waves);
+  L.keys = take(4 * (size_t)r.cells_total);
+  L.hist = take(4 * (size_t)kMpBuckets);
+  L.base = take(4 * (size_t)kMpBuckets);
+  L.cursor = take(4 * (size_t)kMpBuckets);
+  L.waves = take(4 * (size_t)kMpBuckets);
+  L.sorted = take(4 * (size_t)r.cells_total);
   L.full = reduced ? take(sizeof(double) * (size_t)multipole_terms(order, false) *
                           (size_t)r.cells_total)
                    : 0;
@@ -695,12 +694,13 @@ int abacus_nf_multipoles(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   DevBox* dboxes = at<DevBox>(ws, L.boxtab);
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
   MpWork w;
-  w.pencils = r.pencils_total;
-  w.wave_count = at<int32_t>(ws, L.wave_count);
-  w.wave_base = at<int32_t>(ws, L.wave_base);
-  w.scan_tmp = at<int32_t>(ws, L.scan);
-  w.waves = at<int4>(ws, L.waves);
-  w.max_waves = L.max_waves;
+  w.cells = r.cells_total;
+  w.keys = at<int32_t>(ws, L.keys);
+  w.hist = at<int32_t>(ws, L.hist);
+  w.bucket_base = at<int32_t>(ws, L.base);
+  w.cursor = at<int32_t>(ws, L.cursor);
+  w.bucket_waves = at<int32_t>(ws, L.waves);
+  w.sorted = at<int32_t>(ws, L.sorted);
   w.full = reduced ? at<double>(ws, L.full) : nullptr;
   Timer t(4, s);
   ANF_HIP(launch_multipoles(dboxes, nboxes, r.cells_total, order, reduced, w, b->cell_offsets,

@@ -16,20 +16,10 @@
 // atomics, and run-to-run identical results.  When the caller keeps particles
 // in cell order (as the slabs of the paper's code do), the gathers are
 // contiguous.  The per-box statistics are a two-level, fixed-order reduction
-// over chunks of cells.
+// over chunks of 512 cells.
 #include "nf_internal.h"
 
 namespace anf {
-
-__device__ __forceinline__ int find_box_by_cell(const DevBox* __restrict__ boxes, int nb,
-                                                int64_t c) {
-  int lo = 0, hi = nb - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (boxes[mid].cell_base <= c) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 __device__ __forceinline__ int find_box_by_chunk(const DevBox* __restrict__ boxes, int nb,
                                                  int64_t k) {
@@ -151,25 +141,42 @@ __global__ __launch_bounds__(256) void k_kdk_chunks(const DevBox* __restrict__ b
   }
 }
 
-// Stage 2: one thread per box folds its chunks in order.
-__global__ void k_kdk_boxes(const DevBox* __restrict__ boxes, int nboxes,
-                            const double* __restrict__ part, double* __restrict__ box_stats) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nboxes) return;
+// Stage 2: one block per box folds its chunks, strided over the threads and
+// then through a fixed tree.
+__global__ __launch_bounds__(256) void k_kdk_boxes(const DevBox* __restrict__ boxes,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ box_stats) {
+  __shared__ double s_min[256], s_sum[256], s_max[256];
+  const int b = blockIdx.x;
   const int64_t K = boxes[b].K;
   const int64_t nchunks = (K * K * K + kKdkChunk - 1) / kKdkChunk;
   double mn = __builtin_inf(), sm = 0.0, mx = 0.0;
-  for (int64_t j = 0; j < nchunks; ++j) {
+  for (int64_t j = threadIdx.x; j < nchunks; j += blockDim.x) {
     const double* p = part + 3 * (boxes[b].chunk_base + j);
     mn = p[0] < mn ? p[0] : mn;
     sm += p[1];
     mx = p[2] > mx ? p[2] : mx;
   }
-  const int64_t n = boxes[b].n;
-  box_stats[4 * b] = mn;
-  box_stats[4 * b + 1] = n > 0 ? sqrt(sm / (double)n) : 0.0;
-  box_stats[4 * b + 2] = mx;
-  box_stats[4 * b + 3] = (double)n;
+  s_min[threadIdx.x] = mn;
+  s_sum[threadIdx.x] = sm;
+  s_max[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      const int o = threadIdx.x + h;
+      s_min[threadIdx.x] = s_min[o] < s_min[threadIdx.x] ? s_min[o] : s_min[threadIdx.x];
+      s_sum[threadIdx.x] += s_sum[o];
+      s_max[threadIdx.x] = s_max[o] > s_max[threadIdx.x] ? s_max[o] : s_max[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t n = boxes[b].n;
+    box_stats[4 * b] = s_min[0];
+    box_stats[4 * b + 1] = n > 0 ? sqrt(s_sum[0] / (double)n) : 0.0;
+    box_stats[4 * b + 2] = s_max[0];
+    box_stats[4 * b + 3] = (double)n;
+  }
 }
 
 hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t cells_total,
@@ -188,8 +195,8 @@ hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t cells_tota
   hipLaunchKernelGGL(k_kdk_chunks, dim3((unsigned)w.chunks), dim3(256), 0, s, boxes, nboxes, off,
                      w.cell_sumsq, w.cell_amax, w.chunk_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_kdk_boxes, dim3((unsigned)((nboxes + 63) / 64)), dim3(64), 0, s, boxes,
-                     nboxes, w.chunk_part, box_stats);
+  hipLaunchKernelGGL(k_kdk_boxes, dim3((unsigned)nboxes), dim3(256), 0, s, boxes, w.chunk_part,
+                     box_stats);
   return hipGetLastError();
 }
 

@@ -8,25 +8,28 @@
 // formed from the stored FP32 cell-relative offsets.
 //
 // How it maps to CDNA4:
-//   * a work wave covers a run of consecutive cells of one pencil; each cell
-//     gets min(64, ceil(n/8)) lanes and each lane sums a contiguous segment of
-//     the cell's particles, so every lane works on at least a few particles and
-//     no cell is split across waves;
-//   * a lane keeps its partial moments in VGPRs (two passes over the segment
-//     when the basis is too large for the register file, split by the power
-//     of x), then the wave reduces the lanes of each cell through LDS, a chunk
-//     of terms at a time, with one lane per (cell, term) adding its cell's rows
-//     in lane order -- a fixed order, so results are run-to-run deterministic;
-//   * each (cell, term) result is scaled by w^(a+b+c) and written once; the
-//     writes of one cell row are contiguous across lanes.
+//   * each cell gets L lanes (a power of two, about n/32 of them, at most 64)
+//     and each lane sums `per` = ceil(n/L) consecutive particles of the cell;
+//   * cells are bucketed by (L, per) with a counting sort, and a work wave
+//     takes 64/L cells of one bucket, so all 64 lanes of a wave do the same
+//     number of particles -- the balance the paper gets from its "step-down"
+//     remainder iterations;
+//   * a lane keeps its partial moments in FP64 VGPRs (passes of at most 64
+//     terms, split by the power of x), then each cell's L lanes are added in
+//     registers with a butterfly of lane shuffles -- a fixed pairwise order,
+//     so results are run-to-run deterministic whatever wave a cell lands in;
+//   * the first lane of each cell scales the sums by w^(a+b+c) and writes them.
 // The reduced basis is a second, HBM-bound pass over the complete rows.
 #include "nf_internal.h"
 
 namespace anf {
 
-constexpr int kMpMinSeg = 8;   // particles per lane before a cell gets another lane
-constexpr int kMpChunk = 16;   // terms reduced per LDS round
-constexpr int kMpStride = kMpChunk + 1;
+constexpr int kMpSeg = 32;     // target particles per lane
+// Buckets: (log2 L, per) for per <= kMpSeg, then one bucket of cells that need
+// 64 lanes and more than kMpSeg particles per lane, then the empty cells.
+constexpr int kMpGiant = 7 * (kMpSeg + 1);
+constexpr int kMpEmpty = kMpGiant + 1;
+static_assert(kMpEmpty + 2 <= kMpBuckets && kMpEmpty + 2 <= 256, "bucket arrays and scan");
 
 __host__ __device__ constexpr int mp_terms_a(int p, int a0, int a1) {
   int t = 0;
@@ -34,20 +37,25 @@ __host__ __device__ constexpr int mp_terms_a(int p, int a0, int a1) {
   return t;
 }
 
-// First power of x of the second pass: the split that keeps the larger pass
-// smallest (one pass when every term fits in 96 accumulators).
-__host__ __device__ constexpr int mp_split(int p) {
-  if (mp_terms_a(p, 0, p) <= 96) return p + 1;
-  int best = p + 1, best_max = mp_terms_a(p, 0, p);
-  for (int a1 = 1; a1 <= p; ++a1) {
-    const int lo = mp_terms_a(p, 0, a1 - 1), hi = mp_terms_a(p, a1, p);
-    const int m = lo > hi ? lo : hi;
-    if (m < best_max) {
-      best_max = m;
-      best = a1;
+// Passes over a lane's particles: the terms are split by the power of x into
+// consecutive ranges of at most mp_max_acc terms (greedy), so the partial sums
+// of one pass fit in VGPRs with room for three waves per SIMD (p = 8: 45 + 64
+// + 56 terms in three passes).
+__host__ __device__ constexpr int mp_max_acc(int p) { return p < 0 ? 0 : 64; }
+
+// First power of x of pass `k` (pass k covers [mp_pass_a0(p, k), mp_pass_a0(p, k+1) - 1]);
+// p + 1 once the passes are exhausted.
+__host__ __device__ constexpr int mp_pass_a0(int p, int k) {
+  int a = 0;
+  for (int pass = 0; pass < k && a <= p; ++pass) {
+    int t = 0;
+    const int start = a;
+    while (a <= p && (a == start || t + (p - a + 1) * (p - a + 2) / 2 <= mp_max_acc(p))) {
+      t += (p - a + 1) * (p - a + 2) / 2;
+      ++a;
     }
   }
-  return best;
+  return a;
 }
 
 int64_t multipole_terms(int p, bool reduced) {
@@ -55,181 +63,262 @@ int64_t multipole_terms(int p, bool reduced) {
   return reduced ? (int64_t)(p + 1) * (p + 1) : (int64_t)mp_terms_a(p, 0, p);
 }
 
-__device__ __forceinline__ int mp_nseg(int n) {
-  if (n <= 0) return 0;
-  const int s = (n + kMpMinSeg - 1) / kMpMinSeg;
-  return s < 64 ? s : 64;
+// Lanes per cell: the power of two nearest above n / kMpSeg, at most 64.
+__device__ __forceinline__ int mp_lanes_log2(int n) {
+  const int want = (n + kMpSeg - 1) / kMpSeg;
+  int l = 0;
+  while (l < 6 && (1 << l) < want) ++l;
+  return l;
 }
 
-// ---- work waves ------------------------------------------------------------
-// wave = {first global cell, end cell, box, 0}: consecutive cells of one pencil
-// with at most 64 lanes' worth of segments and at most 64 cells.
-template <bool kEmit>
-__device__ int mp_walk_pencil(const int32_t* __restrict__ off, int cell0, int K, int b,
-                              int4* __restrict__ out) {
-  int nw = 0, lo = 0, lanes = 0;
-  for (int z = 0; z < K; ++z) {
-    const int ns = mp_nseg(off[cell0 + z + 1] - off[cell0 + z]);
-    if (z > lo && (lanes + ns > 64 || z - lo >= 64)) {
-      if (kEmit) out[nw] = make_int4(cell0 + lo, cell0 + z, b, 0);
-      ++nw;
-      lo = z;
-      lanes = 0;
-    }
-    lanes += ns;
+__device__ __forceinline__ int mp_key(int n) {
+  if (n <= 0) return kMpEmpty;
+  const int l = mp_lanes_log2(n);
+  const int per = (n + (1 << l) - 1) >> l;
+  return per <= kMpSeg ? l * (kMpSeg + 1) + per : kMpGiant;
+}
+
+// Lanes per cell of a bucket (the giant and empty buckets: 64 and 1).
+__host__ __device__ constexpr int mp_key_lanes_log2(int key) {
+  return key == kMpGiant ? 6 : (key == kMpEmpty ? 0 : key / (kMpSeg + 1));
+}
+
+// ---- planning: counting sort of the cells by bucket --------------------------
+
+__global__ __launch_bounds__(256) void k_mp_classify(const int32_t* __restrict__ off,
+                                                     int64_t cells, int32_t* __restrict__ key_out,
+                                                     int32_t* __restrict__ hist) {
+  __shared__ int local[kMpEmpty + 1];
+  for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x) local[k] = 0;
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < cells) {
+    const int key = mp_key(off[c + 1] - off[c]);
+    key_out[c] = key;
+    atomicAdd(&local[key], 1);
   }
-  if (kEmit) out[nw] = make_int4(cell0 + lo, cell0 + K, b, 0);
-  return nw + 1;
+  __syncthreads();
+  for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x)
+    if (local[k]) atomicAdd(&hist[k], local[k]);
 }
 
-__global__ __launch_bounds__(64) void k_mp_count(const DevBox* __restrict__ boxes, int nboxes,
-                                                 int64_t pencils, const int32_t* __restrict__ off,
-                                                 int32_t* __restrict__ counts) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pencils) return;
-  const int b = nboxes == 1 ? 0 : find_box_by_pencil(boxes, nboxes, (int)p);
-  const int K = boxes[b].K;
-  const int local = (int)p - boxes[b].pencil_base;
-  counts[p] = mp_walk_pencil<false>(off, boxes[b].cell_base + local * K, K, b, nullptr);
+// One block of 256 threads: bucket bases, cursors, and the first wave of every
+// bucket (64 / L cells per wave), by two exclusive scans in LDS;
+// base[kMpEmpty + 1] = cells, waves[kMpEmpty + 1] = total waves.
+__global__ __launch_bounds__(256) void k_mp_buckets(const int32_t* __restrict__ hist,
+                                                    int32_t* __restrict__ base,
+                                                    int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ waves) {
+  __shared__ int sc[256], sw[256];
+  const int k = threadIdx.x;
+  const int h = k <= kMpEmpty ? hist[k] : 0;
+  const int per_wave = 64 >> mp_key_lanes_log2(k <= kMpEmpty ? k : 0);
+  sc[k] = h;
+  sw[k] = (h + per_wave - 1) / per_wave;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scans
+    const int a = k >= d ? sc[k - d] : 0, b = k >= d ? sw[k - d] : 0;
+    __syncthreads();
+    sc[k] += a;
+    sw[k] += b;
+    __syncthreads();
+  }
+  if (k <= kMpEmpty + 1) {
+    const int cb = k == 0 ? 0 : sc[k - 1], wb = k == 0 ? 0 : sw[k - 1];
+    base[k] = cb;
+    waves[k] = wb;
+    if (k <= kMpEmpty) cursor[k] = cb;
+  }
 }
 
-__global__ __launch_bounds__(64) void k_mp_emit(const DevBox* __restrict__ boxes, int nboxes,
-                                                int64_t pencils, const int32_t* __restrict__ off,
-                                                const int32_t* __restrict__ base,
-                                                int4* __restrict__ waves) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pencils) return;
-  const int b = nboxes == 1 ? 0 : find_box_by_pencil(boxes, nboxes, (int)p);
-  const int K = boxes[b].K;
-  const int local = (int)p - boxes[b].pencil_base;
-  mp_walk_pencil<true>(off, boxes[b].cell_base + local * K, K, b, waves + base[p]);
+// Each block ranks its cells per bucket in LDS and reserves one range per
+// bucket with a single global atomic (the order inside a bucket does not
+// matter: every cell's sums are independent of its position).
+__global__ __launch_bounds__(256) void k_mp_scatter(const int32_t* __restrict__ key_in,
+                                                    int64_t cells, int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ sorted) {
+  __shared__ int cnt[kMpEmpty + 1], start[kMpEmpty + 1];
+  for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x) cnt[k] = 0;
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int key = -1, rank = 0;
+  if (c < cells) {
+    key = key_in[c];
+    rank = atomicAdd(&cnt[key], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x)
+    start[k] = cnt[k] ? atomicAdd(&cursor[k], cnt[k]) : 0;
+  __syncthreads();
+  if (key >= 0) sorted[start[key] + rank] = (int32_t)c;
 }
 
 // ---- the moment kernel ----------------------------------------------------
 
 struct MpShared {
-  double rows[64 * kMpStride];   // one chunk of every lane's partial moments
-  double wpow[20];               // w^n, n = 0..p
-  int cell_row[65];              // first lane (row) of each cell of the wave; [ncells] = rows
-  unsigned char order[1024];     // a + b + c of each complete term
+  double wpow[64 * 9];           // per lane: w^n of its cell's box, n = 0..p (p <= 8)
 };
 
-// Sum the terms with x power in [A0, A1] of this lane's particles, then reduce
-// each cell's lanes and write the scaled results.
+// Add one particle's terms with x power in [A0, A1] to acc.
+template <int P, int A0, int A1, int T>
+__device__ __forceinline__ void mp_add(const float4 r, double (&acc)[T]) {
+  const double x = r.x, y = r.y, z = r.z;
+  double zp[P + 1];
+  zp[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= P - A0; ++k) zp[k] = zp[k - 1] * z;
+  double xa = 1.0;
+#pragma unroll
+  for (int a = 0; a < A0; ++a) xa *= x;
+  int k = 0;
+#pragma unroll
+  for (int a = A0; a <= A1; ++a) {
+    double m = xa;  // x^a y^b, b = 0, 1, ...
+#pragma unroll
+    for (int b = 0; b <= P - a; ++b) {
+#pragma unroll
+      for (int c = 0; c <= P - a - b; ++c) {
+        acc[k] = c == 0 ? acc[k] + m : __builtin_fma(m, zp[c], acc[k]);
+        ++k;
+      }
+      m *= y;
+    }
+    xa *= x;
+  }
+}
+
+// A lane's share of its wave: particles [beg, end) of global cell `cell`
+// (cell < 0: none), lane i of the cell's n = L lanes.
+struct MpLane {
+  int beg, end, cell, i, n;
+};
+
 template <int P, int A0, int A1>
-__device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, int beg, int end,
-                                        MpShared& sh, int lane, int ncells, int64_t cell_lo,
+__device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const MpLane& ln,
+                                        MpShared& sh, int lane, int depth,
                                         double* __restrict__ out) {
+  const int beg = ln.beg, end = ln.end;
   constexpr int T = mp_terms_a(P, A0, A1);
   constexpr int TT = mp_terms_a(P, 0, P);
   constexpr int base = A0 == 0 ? 0 : mp_terms_a(P, 0, A0 - 1);
   double acc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = 0.0;
-  for (int j = beg; j < end; ++j) {
-    const float4 r = rel[j];
-    const double x = r.x, y = r.y, z = r.z;
-    double yp[P + 1], zp[P + 1];
-    yp[0] = 1.0;
-    zp[0] = 1.0;
+  // Particles in groups of kG, double-buffered: the loads of the next group
+  // are issued before the arithmetic of the current one (scheduling barriers
+  // keep the compiler from sinking them), so a group's memory latency hides
+  // behind the previous group's arithmetic.  Indices are clamped to the
+  // segment; a group past its end is redone by the tail loop.
+  constexpr int kG = 2;
+  const int last = end - 1;
+  float ax[kG], ay[kG], az[kG], bx[kG], by[kG], bz[kG];
+  const float* f = reinterpret_cast<const float*>(rel);
+  auto load = [&](float (&x)[kG], float (&y)[kG], float (&z)[kG], int at) {
 #pragma unroll
-    for (int k = 1; k <= P; ++k) {
-      yp[k] = yp[k - 1] * y;
-      zp[k] = zp[k - 1] * z;
+    for (int g = 0; g < kG; ++g) {
+      const int64_t q = 4 * (int64_t)(at + g < last ? at + g : last);
+      x[g] = f[q];
+      y[g] = f[q + 1];
+      z[g] = f[q + 2];
     }
-    double xa = 1.0;
+  };
+  auto add = [&](const float (&x)[kG], const float (&y)[kG], const float (&z)[kG]) {
 #pragma unroll
-    for (int a = 0; a < A0; ++a) xa *= x;
-    int k = 0;
-#pragma unroll
-    for (int a = A0; a <= A1; ++a) {
-#pragma unroll
-      for (int b = 0; b <= P - a; ++b) {
-        const double m = a == 0 ? yp[b] : xa * yp[b];
-#pragma unroll
-        for (int c = 0; c <= P - a - b; ++c) {
-          acc[k] = c == 0 ? acc[k] + m : __builtin_fma(m, zp[c], acc[k]);
-          ++k;
-        }
-      }
-      xa *= x;
+    for (int g = 0; g < kG; ++g) {
+      mp_add<P, A0, A1>(make_float4(x[g], y[g], z[g], 0.f), acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  int j = beg;
+  if (j + kG <= end) {
+    load(ax, ay, az, j);
+    while (true) {
+      load(bx, by, bz, j + kG);
+      __builtin_amdgcn_sched_barrier(0);
+      add(ax, ay, az);
+      j += kG;
+      if (j + kG > end) break;
+      load(ax, ay, az, j + kG);
+      __builtin_amdgcn_sched_barrier(0);
+      add(bx, by, bz);
+      j += kG;
+      if (j + kG > end) break;
     }
   }
-  // Reduce chunk by chunk: lane rows go to LDS, then lane q adds the rows of
-  // cell q / CH for term q % CH, in row order.
+  for (; j < end; ++j) mp_add<P, A0, A1>(rel[j], acc);
+  // Add each cell's L lanes in registers with a butterfly over its aligned
+  // block (lane i takes lane i ^ h for h = 1, 2, ..., L/2: a fixed pairwise
+  // order), then the block's first lane scales by w^(a+b+c) and writes the
+  // row.  An empty cell's lane writes zeros.
+  for (int h = 1; h < ln.n; h <<= 1) {
 #pragma unroll
-  for (int t0 = 0; t0 < T; t0 += kMpChunk) {
-    constexpr int kCh = kMpChunk;
-#pragma unroll
-    for (int t = 0; t < kCh; ++t)
-      if (t0 + t < T) sh.rows[lane * kMpStride + t] = acc[t0 + t];
-    __syncthreads();
-    const int ch = T - t0 < kCh ? T - t0 : kCh;
-    for (int q = lane; q < ncells * ch; q += 64) {
-      const int ci = q / ch, t = q - (q / ch) * ch;
-      const int r0 = sh.cell_row[ci], r1 = sh.cell_row[ci + 1];
-      double s = 0.0;
-      for (int r = r0; r < r1; ++r) s += sh.rows[r * kMpStride + t];
-      const int g = base + t0 + t;
-      out[(cell_lo + ci) * TT + g] = s * sh.wpow[sh.order[g]];
-    }
-    __syncthreads();
+    for (int t = 0; t < T; ++t) acc[t] += __shfl_xor(acc[t], h, 64);
   }
-}
-
-template <int P>
-__global__ __launch_bounds__(64) void k_multipoles(const DevBox* __restrict__ boxes,
-                                                   const int4* __restrict__ waves,
-                                                   const int32_t* __restrict__ n_waves_ptr,
-                                                   const int32_t* __restrict__ off,
-                                                   const float4* __restrict__ rel,
-                                                   double* __restrict__ out) {
-  __shared__ MpShared sh;
-  constexpr int A1 = mp_split(P);
-  const int lane = threadIdx.x;
-  {
+  if (ln.cell >= 0 && ln.i == 0) {
+    double* dst = out + (int64_t)ln.cell * TT + base;
+    const double* wp = sh.wpow + lane * 9;
     int k = 0;
 #pragma unroll
-    for (int a = 0; a <= P; ++a)
+    for (int a = A0; a <= A1; ++a)
 #pragma unroll
       for (int b = 0; b <= P - a; ++b)
 #pragma unroll
         for (int c = 0; c <= P - a - b; ++c) {
-          if ((k & 63) == lane) sh.order[k] = (unsigned char)(a + b + c);
+          dst[k] = acc[k] * wp[a + b + c];
           ++k;
         }
   }
-  const int n_waves = __builtin_amdgcn_readfirstlane(*n_waves_ptr);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_multipoles(const DevBox* __restrict__ boxes, int nboxes,
+                                                   const int32_t* __restrict__ bucket_base,
+                                                   const int32_t* __restrict__ bucket_waves,
+                                                   const int32_t* __restrict__ sorted,
+                                                   const int32_t* __restrict__ off,
+                                                   const float4* __restrict__ rel,
+                                                   double* __restrict__ out) {
+  __shared__ MpShared sh;
+  constexpr int S1 = mp_pass_a0(P, 1), S2 = mp_pass_a0(P, 2), S3 = mp_pass_a0(P, 3);
+  static_assert(mp_pass_a0(P, 4) > P, "at most four passes");
+  static_assert(P <= 8, "order table sized for p <= 8");
+  const int lane = threadIdx.x;
+  const int n_waves = __builtin_amdgcn_readfirstlane(bucket_waves[kMpEmpty + 1]);
   for (int wv = blockIdx.x; wv < n_waves; wv += gridDim.x) {
-    const int4 rec = waves[wv];
-    const int c_lo = __builtin_amdgcn_readfirstlane(rec.x);
-    const int c_hi = __builtin_amdgcn_readfirstlane(rec.y);
-    const int b = __builtin_amdgcn_readfirstlane(rec.z);
-    const int ncells = c_hi - c_lo;
-    // lane -> (cell, segment of that cell's particles)
-    int beg = 0, end = 0, rows = 0;
-    for (int c = c_lo; c < c_hi; ++c) {
-      const int cb = __builtin_amdgcn_readfirstlane(off[c]);
-      const int ce = __builtin_amdgcn_readfirstlane(off[c + 1]);
-      const int ns = mp_nseg(ce - cb);
-      if (lane == c - c_lo) sh.cell_row[lane] = rows;
-      if (lane >= rows && lane < rows + ns) {
-        const int per = (ce - cb + ns - 1) / ns;
-        beg = cb + (lane - rows) * per;
-        end = beg + per < ce ? beg + per : ce;
-      }
-      rows += ns;
+    // the bucket of this wave: the last k with bucket_waves[k] <= wv
+    int lo = 0, hi = kMpEmpty;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (__builtin_amdgcn_readfirstlane(bucket_waves[mid]) <= wv) lo = mid; else hi = mid - 1;
     }
-    if (lane == 0) sh.cell_row[ncells] = rows;
-    if (lane <= P) {
+    const int key = lo;
+    const int l2 = mp_key_lanes_log2(key);
+    const int L = 1 << l2;
+    const int idx = __builtin_amdgcn_readfirstlane(bucket_base[key]) +
+                    (wv - __builtin_amdgcn_readfirstlane(bucket_waves[key])) * (64 >> l2) +
+                    (lane >> l2);
+    MpLane ln = {0, 0, -1, lane & (L - 1), L};
+    if (idx < bucket_base[key + 1]) {
+      const int c = sorted[idx];
+      const int cb = off[c], ce = off[c + 1];
+      const int per = (ce - cb + L - 1) >> l2;
+      ln.beg = cb + ln.i * per < ce ? cb + ln.i * per : ce;
+      ln.end = ln.beg + per < ce ? ln.beg + per : ce;
+      ln.cell = c;
+      const int b = nboxes == 1 ? 0 : find_box_by_cell(boxes, nboxes, c);
       const double w = boxes[b].width;
       double v = 1.0;
-      for (int k = 0; k < lane; ++k) v *= w;
-      sh.wpow[lane] = v;
+#pragma unroll
+      for (int o = 0; o <= P; ++o) {
+        sh.wpow[lane * 9 + o] = v;
+        v *= w;
+      }
     }
     __syncthreads();
-    mp_pass<P, 0, A1 - 1>(rel, beg, end, sh, lane, ncells, c_lo, out);
-    if constexpr (A1 <= P) mp_pass<P, A1, P>(rel, beg, end, sh, lane, ncells, c_lo, out);
+    mp_pass<P, 0, S1 - 1>(rel, ln, sh, lane, l2, out);
+    if constexpr (S1 <= P) mp_pass<P, S1, S2 - 1>(rel, ln, sh, lane, l2, out);
+    if constexpr (S2 <= P) mp_pass<P, S2, S3 - 1>(rel, ln, sh, lane, l2, out);
+    if constexpr (S3 <= P) mp_pass<P, S3, P>(rel, ln, sh, lane, l2, out);
   }
 }
 
@@ -292,40 +381,42 @@ __global__ __launch_bounds__(256) void k_mp_reduce(const double* __restrict__ fu
 // ---- host launch -------------------------------------------------------------
 
 template <int P>
-static hipError_t launch_mp_t(const DevBox* boxes, const MpWork& w, const int32_t* off,
-                              const float* rel, double* full, hipStream_t s) {
+static hipError_t launch_mp_t(const DevBox* boxes, int nboxes, const MpWork& w,
+                              const int32_t* off, const float* rel, double* full, hipStream_t s) {
   const void* fn = reinterpret_cast<const void*>(&k_multipoles<P>);
   int blocks = persistent_blocks(fn, 64);
-  if ((int64_t)blocks > w.max_waves) blocks = (int)(w.max_waves > 0 ? w.max_waves : 1);
-  hipLaunchKernelGGL(k_multipoles<P>, dim3(blocks), dim3(64), 0, s, boxes, w.waves,
-                     w.wave_base + w.pencils, off, reinterpret_cast<const float4*>(rel), full);
+  if ((int64_t)blocks > w.cells) blocks = (int)(w.cells > 0 ? w.cells : 1);
+  hipLaunchKernelGGL(k_multipoles<P>, dim3(blocks), dim3(64), 0, s, boxes, nboxes, w.bucket_base,
+                     w.bucket_waves, w.sorted, off, reinterpret_cast<const float4*>(rel), full);
   return hipGetLastError();
 }
 
 hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_total, int order,
                              bool reduced, const MpWork& w, const int32_t* off, const float* rel,
                              double* out, hipStream_t s) {
-  const unsigned pg = (unsigned)((w.pencils + 63) / 64);
-  hipLaunchKernelGGL(k_mp_count, dim3(pg), dim3(64), 0, s, boxes, nboxes, w.pencils, off,
-                     w.wave_count);
-  hipError_t e = hipGetLastError();
+  if (cells_total <= 0) return hipSuccess;
+  hipError_t e = fill_i32(w.hist, 0, kMpBuckets, s);
   if (e != hipSuccess) return e;
-  if ((e = exclusive_scan(w.wave_count, w.wave_base, w.pencils, w.scan_tmp, s)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_mp_emit, dim3(pg), dim3(64), 0, s, boxes, nboxes, w.pencils, off,
-                     w.wave_base, w.waves);
+  const unsigned cg = (unsigned)((cells_total + 255) / 256);
+  hipLaunchKernelGGL(k_mp_classify, dim3(cg), dim3(256), 0, s, off, cells_total, w.keys, w.hist);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mp_buckets, dim3(1), dim3(256), 0, s, w.hist, w.bucket_base, w.cursor,
+                     w.bucket_waves);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mp_scatter, dim3(cg), dim3(256), 0, s, w.keys, cells_total, w.cursor,
+                     w.sorted);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   double* full = reduced ? w.full : out;
   switch (order) {
-    case 0: e = launch_mp_t<0>(boxes, w, off, rel, full, s); break;
-    case 1: e = launch_mp_t<1>(boxes, w, off, rel, full, s); break;
-    case 2: e = launch_mp_t<2>(boxes, w, off, rel, full, s); break;
-    case 3: e = launch_mp_t<3>(boxes, w, off, rel, full, s); break;
-    case 4: e = launch_mp_t<4>(boxes, w, off, rel, full, s); break;
-    case 5: e = launch_mp_t<5>(boxes, w, off, rel, full, s); break;
-    case 6: e = launch_mp_t<6>(boxes, w, off, rel, full, s); break;
-    case 7: e = launch_mp_t<7>(boxes, w, off, rel, full, s); break;
-    default: e = launch_mp_t<8>(boxes, w, off, rel, full, s); break;
+    case 0: e = launch_mp_t<0>(boxes, nboxes, w, off, rel, full, s); break;
+    case 1: e = launch_mp_t<1>(boxes, nboxes, w, off, rel, full, s); break;
+    case 2: e = launch_mp_t<2>(boxes, nboxes, w, off, rel, full, s); break;
+    case 3: e = launch_mp_t<3>(boxes, nboxes, w, off, rel, full, s); break;
+    case 4: e = launch_mp_t<4>(boxes, nboxes, w, off, rel, full, s); break;
+    case 5: e = launch_mp_t<5>(boxes, nboxes, w, off, rel, full, s); break;
+    case 6: e = launch_mp_t<6>(boxes, nboxes, w, off, rel, full, s); break;
+    case 7: e = launch_mp_t<7>(boxes, nboxes, w, off, rel, full, s); break;
+    default: e = launch_mp_t<8>(boxes, nboxes, w, off, rel, full, s); break;
   }
   if (e != hipSuccess || !reduced) return e;
   const int64_t threads = cells_total * (int64_t)(order + 1) * (order + 1);

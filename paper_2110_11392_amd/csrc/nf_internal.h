@@ -138,6 +138,16 @@ __device__ __forceinline__ int find_box_by_pencil(const DevBox* __restrict__ box
   return lo;
 }
 
+__device__ __forceinline__ int find_box_by_cell(const DevBox* __restrict__ boxes, int nb,
+                                                int64_t c) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (boxes[mid].cell_base <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---- launch helpers implemented in the .hip files (host side) -------------
 
 // common.hip
@@ -152,14 +162,16 @@ hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* t
 
 // multipoles.hip
 constexpr int kMaxMultipoleOrder = 8;
+constexpr int kMpBuckets = 240;  // bucket table entries (the kernel uses 234)
 struct MpWork {
-  int64_t pencils;
-  int32_t* wave_count;  // pencils: work waves per pencil
-  int32_t* wave_base;   // pencils + 1: exclusive scan; [pencils] = total waves
-  int32_t* scan_tmp;
-  int4* waves;          // max_waves records {first cell, end cell, box, 0}
-  int64_t max_waves;
-  double* full;         // cells_total x complete terms (only for the reduced basis)
+  int64_t cells;
+  int32_t* keys;          // cells: bucket of each cell
+  int32_t* hist;          // kMpBuckets: cells per bucket
+  int32_t* bucket_base;   // kMpBuckets: first sorted slot of each bucket (+ total)
+  int32_t* cursor;        // kMpBuckets: scatter cursors
+  int32_t* bucket_waves;  // kMpBuckets: first work wave of each bucket (+ total)
+  int32_t* sorted;        // cells: cell ids sorted by bucket
+  double* full;           // cells_total x complete terms (only for the reduced basis)
 };
 int64_t multipole_terms(int p, bool reduced);
 hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_total, int order,
@@ -167,7 +179,7 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
                              const float* rel, double* out, hipStream_t s);
 
 // kdk.hip
-constexpr int kKdkChunk = 8192;  // cells per statistics chunk
+constexpr int kKdkChunk = 512;   // cells per statistics chunk
 struct KdkWork {
   double* cell_sumsq;   // cells_total: sum |v'|^2 per cell
   double* cell_amax;    // cells_total: max |a| per cell

@@ -342,40 +342,59 @@ __device__ __forceinline__ double mp_fact(int n) {
   return f;
 }
 
+// Each block first tabulates, in LDS, the sources and coefficients of every
+// reduced term (at most 15 each for p <= 8), then its threads take (cell,
+// reduced term) pairs -- consecutive threads share a cell row and write
+// consecutive outputs.
+constexpr int kMpRedSrc = 16;
+
 __global__ __launch_bounds__(256) void k_mp_reduce(const double* __restrict__ full, int p,
                                                    int64_t cells, double* __restrict__ out) {
+  __shared__ double coef[81 * kMpRedSrc];
+  __shared__ short src[81 * kMpRedSrc];
+  __shared__ int cnt[81];
   const int RT = (p + 1) * (p + 1);
   const int TT = mp_terms_a(p, 0, p);
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= cells * RT) return;
-  const int64_t cell = idx / RT;
-  int r = (int)(idx - cell * RT);
-  // decode reduced term r -> (a, b, c0), enumerated a, b, then c0 in {0, 1}
-  int a = 0, b = 0, c0 = 0;
-  for (a = 0; a <= p; ++a) {
-    int here = 0;
-    for (int bb = 0; bb <= p - a; ++bb) here += (p - a - bb >= 1) ? 2 : 1;
-    if (r < here) break;
-    r -= here;
-  }
-  for (b = 0; b <= p - a; ++b) {
-    const int here = (p - a - b >= 1) ? 2 : 1;
-    if (r < here) break;
-    r -= here;
-  }
-  c0 = r;
-  const double* row = full + cell * TT;
-  double sum = 0.0;
-  for (int m = 0; 2 * m <= a + b; ++m)
-    for (int i = 0; i <= m; ++i) {
-      const int sa = a - 2 * i, sb = b - 2 * (m - i), sc = c0 + 2 * m;
-      if (sa < 0 || sb < 0) continue;
-      const double coef = ((m & 1) ? -1.0 : 1.0) * (mp_fact(m) / (mp_fact(i) * mp_fact(m - i))) *
-                          mp_fact(a) * mp_fact(b) * mp_fact(c0) /
-                          (mp_fact(sa) * mp_fact(sb) * mp_fact(sc));
-      sum += coef * row[mp_index(p, sa, sb, sc)];
+  for (int r = threadIdx.x; r < RT; r += blockDim.x) {
+    // decode reduced term r -> (a, b, c0), enumerated a, b, then c0 in {0, 1}
+    int rr = r, a = 0, b = 0;
+    for (a = 0; a <= p; ++a) {
+      int here = 0;
+      for (int bb = 0; bb <= p - a; ++bb) here += (p - a - bb >= 1) ? 2 : 1;
+      if (rr < here) break;
+      rr -= here;
     }
-  out[idx] = sum;
+    for (b = 0; b <= p - a; ++b) {
+      const int here = (p - a - b >= 1) ? 2 : 1;
+      if (rr < here) break;
+      rr -= here;
+    }
+    const int c0 = rr;
+    int n = 0;
+    for (int m = 0; 2 * m <= a + b; ++m)
+      for (int i = 0; i <= m; ++i) {
+        const int sa = a - 2 * i, sb = b - 2 * (m - i), sc = c0 + 2 * m;
+        if (sa < 0 || sb < 0) continue;
+        coef[r * kMpRedSrc + n] = ((m & 1) ? -1.0 : 1.0) *
+                                  (mp_fact(m) / (mp_fact(i) * mp_fact(m - i))) * mp_fact(a) *
+                                  mp_fact(b) * mp_fact(c0) /
+                                  (mp_fact(sa) * mp_fact(sb) * mp_fact(sc));
+        src[r * kMpRedSrc + n] = (short)mp_index(p, sa, sb, sc);
+        ++n;
+      }
+    cnt[r] = n;
+  }
+  __syncthreads();
+  const int64_t total = cells * RT;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cell = idx / RT;
+    const int r = (int)(idx - cell * RT);
+    const double* row = full + cell * TT;
+    double sum = 0.0;
+    for (int e = 0; e < cnt[r]; ++e) sum += coef[r * kMpRedSrc + e] * row[src[r * kMpRedSrc + e]];
+    out[idx] = sum;
+  }
 }
 
 // ---- host launch -------------------------------------------------------------
@@ -420,8 +439,10 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
   }
   if (e != hipSuccess || !reduced) return e;
   const int64_t threads = cells_total * (int64_t)(order + 1) * (order + 1);
-  hipLaunchKernelGGL(k_mp_reduce, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, w.full,
-                     order, cells_total, out);
+  int64_t blocks = (threads + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_mp_reduce, dim3((unsigned)blocks), dim3(256), 0, s, w.full, order,
+                     cells_total, out);
   return hipGetLastError();
 }
 

@@ -172,8 +172,9 @@ class Stepper:
 def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
     """The widened rows, each timed by the library's own HIP events over `reps`
     launches outside the main step: the density estimate fused into the
-    forward kernel, the Plummer law, the cell multipoles (p = 8, complete and
-    reduced) and the kick-drift step.  Returns per-row figures."""
+    forward kernel, the Plummer law, the FP64 pair kernel, the cell multipoles
+    (p = 8, complete and reduced) and the kick-drift step.  Returns per-row
+    figures."""
     import numpy as np
     from paper_2110_11392_amd import synth
     nf = st.nf
@@ -209,6 +210,11 @@ def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
     plum = kernel_ms(0, lambda: nfp.forces(st.binned, accumulation, out=st.acc))
     rows["plummer"] = {"forward_ms": plum}
     del nfp
+    # the FP64 pair kernel (built-in shape, whole work items)
+    acc64 = torch.empty((nf.n_total, 3), dtype=torch.float64, device=dev)
+    f64 = kernel_ms(0, lambda: nf.forces_f64(st.binned, out=acc64))
+    rows["fp64_forward"] = {"forward_ms": f64, "vs_fp32": f64 / fwd}
+    del acc64
     # multipoles, p = 8
     n, cells = nf.n_total, nf.cells_total
     out_c = torch.empty((cells, 165), dtype=torch.float64, device=dev)

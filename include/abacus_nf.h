@@ -158,6 +158,20 @@ int abacus_nf_forces(const abacus_nf_box *boxes, int nboxes, const abacus_nf_bin
                      uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * abacus_nf_forces_f64 -- the same near-field accelerations with every
+ * operation after the stored FP32 cell offsets done in FP64 (the paper's
+ * double-precision build option): separations, r^2, 1/r (hardware estimate
+ * plus two Newton steps), Eq. 3 with the min hand-off or, with
+ * ABACUS_NF_PLUMMER, Eq. 2, and a plain FP64 sum per sink.  The result is the
+ * near field of the stored positions to FP64 rounding.
+ *   acc    n_total x 3 FP64 output in ORIGINAL particle order, box units.
+ *   flags  0 or ABACUS_NF_PLUMMER (no accumulation modes, density or pair
+ *          counting).  Same workspace as abacus_nf_forces.
+ */
+int abacus_nf_forces_f64(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                         double *acc, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * abacus_nf_forces_vjp -- vector-Jacobian product of the accelerations.
  * For a cotangent w (n_total x 3 FP32, original order) returns
  *   grad_k = d/dx_k sum_i w_i . a_i

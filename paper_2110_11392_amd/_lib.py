@@ -63,7 +63,8 @@ EXPORTS = ("abacus_nf_layout", "abacus_nf_workspace_bytes", "abacus_nf_bin", "ab
            "abacus_nf_get_tuning", "abacus_nf_set_tuning", "abacus_nf_timing_enable",
            "abacus_nf_timing_read", "abacus_nf_timing_reset", "abacus_nf_multipole_terms",
            "abacus_nf_multipoles_workspace_bytes", "abacus_nf_multipoles",
-           "abacus_nf_kick_drift_workspace_bytes", "abacus_nf_kick_drift", "abacus_nf_timestep")
+           "abacus_nf_kick_drift_workspace_bytes", "abacus_nf_kick_drift", "abacus_nf_timestep",
+           "abacus_nf_forces_f64")
 
 _lib = None
 
@@ -92,6 +93,7 @@ def load() -> ctypes.CDLL:
     lib.abacus_nf_bin.argtypes = [BoxP, ctypes.c_int, vp, BinnedP, vp, sz, vp]
     lib.abacus_nf_forces.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, vp, u32, vp, sz, vp]
     lib.abacus_nf_forces_vjp.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, u32, vp, sz, vp]
+    lib.abacus_nf_forces_f64.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp]
     TuneP = ctypes.POINTER(Tuning)
     lib.abacus_nf_autotune.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp, TuneP,
                                        TuneP]

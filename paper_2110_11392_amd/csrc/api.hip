@@ -96,7 +96,9 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = f
       const double ep = x.eps_plummer * cpl;
       d.far_mode = kFarAll;
       d.guard = (float)(ep * ep);
+      d.eps_cells64 = ep;
     } else {
+      d.eps_cells64 = e;
       // Points of cells two apart on an axis are >= 1 cell apart; with eps below
       // half a cell no rounding can bring such a pair inside eps.
       d.far_mode = e < 0.5 ? kFarApart : kFarNone;
@@ -399,6 +401,35 @@ int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_bin
   if (momentum)
     ANF_HIP(launch_momentum(dboxes, nboxes, r.max_box_n, acc, at<double>(ws, L.mom), momentum, s),
             "momentum reduction");
+  return ABACUS_NF_OK;
+}
+
+int abacus_nf_forces_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                         double* acc, uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  if (flags & ~ABACUS_NF_PLUMMER) return ABACUS_NF_EINVAL;
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
+  if (rc) return rc;
+  if (!binned_ok(b) || (r.n_total > 0 && !acc)) return ABACUS_NF_EINVAL;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  PlanWork w = plan_work(ws, L);
+  // The FP64 kernel takes whole items only, in the default span.
+  KernelConfig cfg = default_config(0);
+  cfg.split = 0;
+  w.split_items = 0;
+  ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, 1, w, s),
+          "work plan");
+  if (r.n_total > 0) {
+    Timer t(0, s);
+    ANF_HIP(launch_forward_f64(dboxes, w, b->cell_offsets, b->rel, b->perm, acc,
+                               at<float>(ws, L.src_w), r.n_total, s),
+            "FP64 forward pair kernel");
+    t.done();
+  }
   return ABACUS_NF_OK;
 }
 

@@ -107,6 +107,7 @@ struct DevBox {
   double width;         // w = L / K (box units per cell width)
   double box_len;       // L
   double kick, drift;   // kick-drift step factors of this call
+  double eps_cells64;   // the FP64 kernel's softening in cell widths: eps_s (Eq. 3) or eps_p (Eq. 2)
 };
 constexpr int kFarNone = 0, kFarApart = 1, kFarAll = 2;
 
@@ -258,6 +259,10 @@ void clear_config(const TuneKey& k);
 
 // pairs.hip
 // src3: workspace for n_total packed (x, y, z) source records.
+// pairs64.hip: the FP64 forward kernel (whole tasks only: plan it with no splits)
+hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int32_t* off,
+                              const float* rel, const int32_t* perm, double* acc, float* src3,
+                              int64_t n_total, hipStream_t s);
 hipError_t launch_forward(AccMode mode, bool count_pairs, const KernelConfig& cfg,
                           const DevBox* boxes, const PlanWork& w, int64_t pencils_total,
                           const int32_t* cell_offsets, const float* rel, const int32_t* perm,

@@ -1,0 +1,178 @@
+// FP64 variant of the forward pair kernel (the "double precision" build option
+// of the paper's code, as a run-time entry point).
+//
+// What it computes: the same near-field sum as the FP32 kernel -- Eq. 3 with
+// the min hand-off, or Eq. 2 -- with every operation after the FP32 cell
+// offsets in FP64: the separation (exact: an FP32 offset minus an integer
+// cell shift), r^2, 1/r from the hardware estimate refined by two Newton
+// steps, the force law and a plain FP64 sum per sink.  The result is the
+// near field of the stored positions to FP64 rounding.
+//
+// How it maps to CDNA4: the FP32 kernel's work items, task queue and wave
+// structure, with sources still broadcast through SGPRs as packed FP32
+// records and widened per pair; MI355X issues FP64 FMAs at the FP32
+// (non-packed) rate, so the cost is the longer reciprocal square root.
+#include "nf_internal.h"
+
+namespace anf {
+
+static __device__ __forceinline__ int uni64(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+static __device__ __forceinline__ int wrap64(int v, int K) {
+  v += v < 0 ? K : 0;
+  v -= v >= K ? K : 0;
+  return v;
+}
+
+// 1/sqrt(x): hardware estimate, then two Newton steps y <- y (3/2 - x y^2 / 2).
+static __device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double t = (x * y) * y;
+    y = y * __builtin_fma(-0.5, t, 1.5);
+  }
+  return y;
+}
+
+struct Const64 {
+  double c0, c1, c2, g;
+};
+
+template <bool kNear>
+__device__ __forceinline__ void interact64(float sx, float sy, float sz, double qx, double qy,
+                                           double qz, const Const64& k, double& tx, double& ty,
+                                           double& tz) {
+  const double dx = (double)sx - qx;
+  const double dy = (double)sy - qy;
+  const double dz = (double)sz - qz;
+  const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, k.g)));
+  const double rinv = rsqrt64(r2);
+  const double rinv3 = (rinv * rinv) * rinv;
+  double f = rinv3;
+  if (kNear) {
+    const double r = r2 * rinv;
+    const double spline = __builtin_fma(__builtin_fma(k.c2, r, k.c1), r, k.c0);
+    f = spline < rinv3 ? spline : rinv3;
+  }
+  tx = __builtin_fma(f, dx, tx);
+  ty = __builtin_fma(f, dy, ty);
+  tz = __builtin_fma(f, dz, tz);
+}
+
+template <bool kNear>
+__device__ __forceinline__ void sum64(const float* __restrict__ src3, int beg, int end, double qx,
+                                      double qy, double qz, const Const64& k, double& tx,
+                                      double& ty, double& tz) {
+  int j = beg;
+  for (; j + 2 <= end; j += 2) {
+    float c[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) c[u] = src3[3 * j + u];
+    interact64<kNear>(c[0], c[1], c[2], qx, qy, qz, k, tx, ty, tz);
+    interact64<kNear>(c[3], c[4], c[5], qx, qy, qz, k, tx, ty, tz);
+  }
+  for (; j < end; ++j)
+    interact64<kNear>(src3[3 * j], src3[3 * j + 1], src3[3 * j + 2], qx, qy, qz, k, tx, ty, tz);
+}
+
+__global__ __launch_bounds__(256) void k_pair_forward_f64(
+    const DevBox* __restrict__ boxes, const int4* __restrict__ items,
+    const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
+    const int32_t* __restrict__ off, const float4* __restrict__ rel,
+    const float* __restrict__ src3, const int32_t* __restrict__ perm,
+    double* __restrict__ acc_out) {
+  const int lane = threadIdx.x & 63;
+  const int n_tasks = uni64(ctrl[kCtrlNTasks]);
+  while (true) {
+    int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
+    t = uni64(__shfl(t, 0, 64));
+    if (t >= n_tasks) break;
+    const int4 it = items[uni64(tasks[t]) >> kTaskShift];
+    const int b = uni64(it.x & 0xffff), count = uni64(it.x >> 16);
+    const int cx = uni64(it.y & 0xffff), cy = uni64(it.y >> 16);
+    const int za = uni64(it.z & 0xffff), zb = uni64(it.z >> 16);
+    const int first = uni64(it.w);
+    const int K = uni64(boxes[b].K), R = uni64(boxes[b].R);
+    const int cbase = uni64(boxes[b].cell_base);
+    const int far_mode = uni64(boxes[b].far_mode);
+    const double e = boxes[b].eps_cells64;
+    Const64 kc;
+    kc.c0 = 10.0 / (e * e * e);
+    kc.c1 = -15.0 / (e * e * e * e);
+    kc.c2 = 6.0 / (e * e * e * e * e);
+    // Eq. 2: eps_p^2 added to r^2; Eq. 3: a guard that keeps 1/r^3 finite for
+    // coincident points (their d = 0 makes the force 0) and is far below the
+    // square of any FP32-representable separation.
+    kc.g = far_mode == kFarAll ? e * e : 1e-200;
+    const int pencil0 = cbase + (cx * K + cy) * K;
+    const int s = lane < count ? first + lane : -1;
+    int lane_z = za;
+    for (int z = za; z < zb; ++z)
+      if (s >= uni64(off[pencil0 + z + 1])) lane_z = z + 1;
+    const bool active = s >= 0;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) p = rel[s];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int ox = -R; ox <= R; ++ox) {
+      const int sx = wrap64(cx + ox, K);
+      const double qx = (double)p.x - (double)ox;
+      for (int oy = -R; oy <= R; ++oy) {
+        const int sy = wrap64(cy + oy, K);
+        const double qy = (double)p.y - (double)oy;
+        const int col = cbase + (sx * K + sy) * K;
+        const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
+        for (int zu = za - R; zu <= zb + R; ++zu) {
+          const int sz = wrap64(zu, K);
+          const int beg = uni64(off[col + sz]), end = uni64(off[col + sz + 1]);
+          if (beg == end) continue;
+          const int oz = zu - lane_z;
+          const bool near = far_mode == kFarNone ||
+                            (far_mode == kFarApart && col_near && zu >= za - 1 && zu <= zb + 1);
+          if (active && oz >= -R && oz <= R) {
+            const double qz = (double)p.z - (double)oz;
+            if (near)
+              sum64<true>(src3, beg, end, qx, qy, qz, kc, ax, ay, az);
+            else
+              sum64<false>(src3, beg, end, qx, qy, qz, kc, ax, ay, az);
+          }
+        }
+      }
+    }
+    if (active) {
+      const double cpl = boxes[b].cells_per_len;
+      const double iw2 = cpl * cpl;
+      const int64_t i = perm[s];
+      acc_out[3 * i + 0] = ax * iw2;
+      acc_out[3 * i + 1] = ay * iw2;
+      acc_out[3 * i + 2] = az * iw2;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pack_sources64(const float4* __restrict__ rel, int64_t n,
+                                                        float* __restrict__ src3) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const float4 r = rel[s];
+  src3[3 * s + 0] = r.x;
+  src3[3 * s + 1] = r.y;
+  src3[3 * s + 2] = r.z;
+}
+
+hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int32_t* off,
+                              const float* rel, const int32_t* perm, double* acc, float* src3,
+                              int64_t n_total, hipStream_t s) {
+  if (n_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_sources64, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(rel), n_total, src3);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const void* fn = reinterpret_cast<const void*>(&k_pair_forward_f64);
+  const int blocks = persistent_blocks(fn, 256);
+  hipLaunchKernelGGL(k_pair_forward_f64, dim3(blocks), dim3(256), 0, s, boxes, w.items, w.tasks,
+                     w.ctrl, off, reinterpret_cast<const float4*>(rel), src3, perm, acc);
+  return hipGetLastError();
+}
+
+}  // namespace anf

@@ -162,6 +162,21 @@ class NearField:
                    "abacus_nf_forces")
         return acc, mom, pairs
 
+    def forces_f64(self, binned: Binned, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Accelerations (n, 3) in FP64, original order: the FP64 pair kernel."""
+        acc = out if out is not None else torch.empty((self.n_total, 3), dtype=torch.float64,
+                                                      device=self.device)
+        if acc.dtype != torch.float64 or tuple(acc.shape) != (self.n_total, 3) or \
+                not acc.is_contiguous():
+            raise ValueError("out must be a contiguous (n, 3) float64 tensor")
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_forces_f64(self._boxes, self.nboxes, ctypes.byref(cs),
+                                                  _ptr(acc), LAWS[self.law],
+                                                  _ptr(self.workspace), self.workspace_bytes,
+                                                  _stream()),
+                   "abacus_nf_forces_f64")
+        return acc
+
     def forces_vjp(self, binned: Binned, w: torch.Tensor, accumulation: str = "compensated",
                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if w.dtype != torch.float32 or tuple(w.shape) != (self.n_total, 3) or not w.is_contiguous():

@@ -254,3 +254,19 @@ def test_timestep_matches_oracle_on_host():
             arr = (ctypes.c_double * 4)(*stats)
             got = _lib.load().abacus_nf_timestep(arr, 0.5, 2.0, 0.25, eta_h)
             assert got == oracle.timestep(stats, 0.5, 2.0, 0.25, eta_h)
+
+
+def test_fp64_forces_arguments_without_gpu():
+    lib = _lib.load()
+    b = boxes((100, 1.0, 8, 2, 1e-3))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.abacus_nf_workspace_bytes(b, 1, ctypes.byref(nbytes)) == 0
+    fake = ctypes.c_void_p(0x1000)
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    for flags in (_lib.COMPENSATED, _lib.COUNT_PAIRS, 0x80):
+        assert lib.abacus_nf_forces_f64(b, 1, ctypes.byref(binned), fake, flags, fake, nbytes,
+                                        None) == _lib.EINVAL
+    assert lib.abacus_nf_forces_f64(b, 1, ctypes.byref(binned), None, 0, fake, nbytes,
+                                    None) == _lib.EINVAL
+    assert lib.abacus_nf_forces_f64(b, 1, ctypes.byref(binned), fake, _lib.PLUMMER, None, nbytes,
+                                    None) == _lib.EWORKSPACE

@@ -145,3 +145,63 @@ def test_graph_replay_matches_eager(anf):
         bd = nf.bin(inputs[(k + 1) % len(inputs)])
         nf.forces(bd)
         torch.cuda.synchronize()
+
+
+def test_graph_replay_of_the_widened_rows(anf):
+    """Binning, forces with the density estimate, the FP64 kernel, multipoles
+    (both bases) and kick-drift captured in one graph: every replay, with state
+    reset and eager work between replays, equals the eager results bit for bit."""
+    boxes = synth.config("C4", scale=6)
+    specs = [anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer, 0.3 * b.box / b.cpd)
+             for b in boxes]
+    nf = anf.NearField(specs)
+    pos0 = torch.from_numpy(np.concatenate([b.pos for b in boxes])).cuda()
+    vel0 = torch.from_numpy(synth.gaussian_weights(nf.n_total, 41) * np.float32(0.01)).cuda()
+    pos, vel = pos0.clone(), vel0.clone()
+    binned = nf.alloc_binned()
+    acc = torch.empty((nf.n_total, 3), dtype=torch.float32, device="cuda")
+    acc64 = torch.empty((nf.n_total, 3), dtype=torch.float64, device="cuda")
+    rho = torch.empty(nf.n_total, dtype=torch.float32, device="cuda")
+    mp_c = torch.empty((nf.cells_total, 165), dtype=torch.float64, device="cuda")
+    mp_r = torch.empty((nf.cells_total, 81), dtype=torch.float64, device="cuda")
+    outs = {}
+
+    def step():
+        nf.bin(pos, out=binned)
+        nf.forces(binned, out=acc, density_out=rho)
+        nf.forces_f64(binned, out=acc64)
+        nf.multipoles(binned, 8, out=mp_c)
+        nf.multipoles(binned, 8, reduced=True, out=mp_r)
+        outs["stats"] = nf.kick_drift(binned, pos, vel, acc, 0.01, 0.002, cell_stats=True)
+
+    def snapshot():
+        cs, bs = outs["stats"]
+        return [t.detach().cpu().numpy().copy() for t in
+                (acc, acc64, rho, mp_c, mp_r, pos, vel, cs, bs)]
+
+    step()                    # eager reference (also allocates the lazy workspaces)
+    torch.cuda.synchronize()
+    ref = snapshot()
+    pos.copy_(pos0)
+    vel.copy_(vel0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    say("[graph] capture of the widened rows")
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        pos.copy_(pos0)
+        vel.copy_(vel0)
+        graph.replay()
+        torch.cuda.synchronize()
+        say(f"[graph] widened replay {rep}")
+        for k, (x, y) in enumerate(zip(snapshot(), ref)):
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), (rep, k)
+        bd = nf.bin(pos0)
+        nf.multipoles(bd, 4)
+        torch.cuda.synchronize()

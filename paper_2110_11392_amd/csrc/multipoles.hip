@@ -8,8 +8,12 @@
 // formed from the stored FP32 cell-relative offsets.
 //
 // How it maps to CDNA4:
-//   * each cell gets L lanes (a power of two, about n/32 of them, at most 64)
+//   * each cell gets L lanes (a power of two, about n/16 of them, at most 64)
 //     and each lane sums `per` = ceil(n/L) consecutive particles of the cell;
+//   * a wave first copies its cells' offsets into LDS with coalesced loads (64
+//     consecutive particles per instruction), so the per-lane reads of the
+//     passes hit LDS instead of scattered global lines (cells needing more than
+//     16 particles per lane read global memory directly);
 //   * cells are bucketed by (L, per) with a counting sort, and a work wave
 //     takes 64/L cells of one bucket, so all 64 lanes of a wave do the same
 //     number of particles -- the balance the paper gets from its "step-down"
@@ -24,7 +28,8 @@
 
 namespace anf {
 
-constexpr int kMpSeg = 32;     // target particles per lane
+constexpr int kMpSeg = 16;     // target particles per lane
+constexpr int kMpStage = 64 * kMpSeg;  // particles a wave stages in LDS
 // Buckets: (log2 L, per) for per <= kMpSeg, then one bucket of cells that need
 // 64 lanes and more than kMpSeg particles per lane, then the empty cells.
 constexpr int kMpGiant = 7 * (kMpSeg + 1);
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(256) void k_mp_scatter(const int32_t* __restrict__ 
 // ---- the moment kernel ----------------------------------------------------
 
 struct MpShared {
-  double wpow[64 * 9];           // per lane: w^n of its cell's box, n = 0..p (p <= 8)
+  float x[kMpStage], y[kMpStage], z[kMpStage];  // the wave's staged offsets
 };
 
 // Add one particle's terms with x power in [A0, A1] to acc.
@@ -191,6 +196,8 @@ __device__ __forceinline__ void mp_add(const float4 r, double (&acc)[T]) {
 // (cell < 0: none), lane i of the cell's n = L lanes.
 struct MpLane {
   int beg, end, cell, i, n;
+  int lds;   // first staged slot of [beg, end), or -1 when read from global memory
+  double w;  // cell width of the cell's box
 };
 
 template <int P, int A0, int A1>
@@ -229,6 +236,13 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
       __builtin_amdgcn_sched_barrier(0);
     }
   };
+  if (ln.lds >= 0) {
+    const int cnt = end - beg;
+    const float* sx = sh.x + ln.lds;
+    const float* sy = sh.y + ln.lds;
+    const float* sz = sh.z + ln.lds;
+    for (int m = 0; m < cnt; ++m) mp_add<P, A0, A1>(make_float4(sx[m], sy[m], sz[m], 0.f), acc);
+  } else {
   int j = beg;
   if (j + kG <= end) {
     load(ax, ay, az, j);
@@ -246,6 +260,7 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
     }
   }
   for (; j < end; ++j) mp_add<P, A0, A1>(rel[j], acc);
+  }
   // Add each cell's L lanes in registers with a butterfly over its aligned
   // block (lane i takes lane i ^ h for h = 1, 2, ..., L/2: a fixed pairwise
   // order), then the block's first lane scales by w^(a+b+c) and writes the
@@ -256,7 +271,10 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
   }
   if (ln.cell >= 0 && ln.i == 0) {
     double* dst = out + (int64_t)ln.cell * TT + base;
-    const double* wp = sh.wpow + lane * 9;
+    double wp[P + 1];
+    wp[0] = 1.0;
+#pragma unroll
+    for (int o = 1; o <= P; ++o) wp[o] = wp[o - 1] * ln.w;
     int k = 0;
 #pragma unroll
     for (int a = A0; a <= A1; ++a)
@@ -297,7 +315,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     const int idx = __builtin_amdgcn_readfirstlane(bucket_base[key]) +
                     (wv - __builtin_amdgcn_readfirstlane(bucket_waves[key])) * (64 >> l2) +
                     (lane >> l2);
-    MpLane ln = {0, 0, -1, lane & (L - 1), L};
+    MpLane ln = {0, 0, -1, lane & (L - 1), L, -1, 0.0};
     if (idx < bucket_base[key + 1]) {
       const int c = sorted[idx];
       const int cb = off[c], ce = off[c + 1];
@@ -306,19 +324,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
       ln.end = ln.beg + per < ce ? ln.beg + per : ce;
       ln.cell = c;
       const int b = nboxes == 1 ? 0 : find_box_by_cell(boxes, nboxes, c);
-      const double w = boxes[b].width;
-      double v = 1.0;
-#pragma unroll
-      for (int o = 0; o <= P; ++o) {
-        sh.wpow[lane * 9 + o] = v;
-        v *= w;
+      ln.w = boxes[b].width;
+    }
+    if (key < kMpGiant) {
+      // Stage the wave's cells: cell k of the wave owns slots
+      // [k L per, (k + 1) L per), its lanes read their segments from there.
+      const int per = key - l2 * (kMpSeg + 1);
+      const int first = __builtin_amdgcn_readfirstlane(bucket_base[key]) +
+                        (wv - __builtin_amdgcn_readfirstlane(bucket_waves[key])) * (64 >> l2);
+      const int lim = __builtin_amdgcn_readfirstlane(bucket_base[key + 1]);
+      // lane k fetches the bounds of the wave's cell k, all at once
+      int my_cb = 0, my_n = 0;
+      if (lane < (64 >> l2) && first + lane < lim) {
+        const int c = sorted[first + lane];
+        my_cb = off[c];
+        my_n = off[c + 1] - my_cb;
       }
+      const int ncell = (lim - first) < (64 >> l2) ? (lim - first) : (64 >> l2);
+      // Four cells at a time: their first 64 particles are requested together
+      // so one memory latency covers four cells; longer cells finish after.
+      for (int k = 0; k < ncell; k += 4) {
+        float4 r[4];
+        int cbs[4], ns[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = k + u < ncell;
+          cbs[u] = ok ? __builtin_amdgcn_readlane(my_cb, (k + u) & 63) : 0;
+          ns[u] = ok ? __builtin_amdgcn_readlane(my_n, (k + u) & 63) : 0;
+          if (lane < ns[u]) r[u] = rel[cbs[u] + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int slot = (k + u) * L * per;
+          if (lane < ns[u]) {
+            sh.x[slot + lane] = r[u].x;
+            sh.y[slot + lane] = r[u].y;
+            sh.z[slot + lane] = r[u].z;
+          }
+          for (int m = lane + 64; m < ns[u]; m += 64) {
+            const float4 q = rel[cbs[u] + m];
+            sh.x[slot + m] = q.x;
+            sh.y[slot + m] = q.y;
+            sh.z[slot + m] = q.z;
+          }
+        }
+      }
+      if (ln.cell >= 0) ln.lds = (lane >> l2) * L * per + ln.i * per;
     }
     __syncthreads();
     mp_pass<P, 0, S1 - 1>(rel, ln, sh, lane, l2, out);
     if constexpr (S1 <= P) mp_pass<P, S1, S2 - 1>(rel, ln, sh, lane, l2, out);
     if constexpr (S2 <= P) mp_pass<P, S2, S3 - 1>(rel, ln, sh, lane, l2, out);
     if constexpr (S3 <= P) mp_pass<P, S3, P>(rel, ln, sh, lane, l2, out);
+    __syncthreads();  // the next wave's staging overwrites the slots
   }
 }
 

@@ -89,6 +89,7 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = f
     d.c1 = (float)(-15.0 / (e * e * e * e));
     d.c2 = (float)(6.0 / (e * e * e * e * e));
     d.eps = (float)e;
+    d.near2 = (float)(1.21 * e * e);
     d.ha = (float)(12.0 / (e * e * e * e * e));
     d.hb = (float)(-15.0 / (e * e * e * e));
     if (plummer) {

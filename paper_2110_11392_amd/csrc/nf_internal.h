@@ -108,6 +108,8 @@ struct DevBox {
   double box_len;       // L
   double kick, drift;   // kick-drift step factors of this call
   double eps_cells64;   // the FP64 kernel's softening in cell widths: eps_s (Eq. 3) or eps_p (Eq. 2)
+  float near2;          // (1.1 eps)^2 in cell units: pairs beyond it take 1/r^3 without the select
+  int32_t pad2_;
 };
 constexpr int kFarNone = 0, kFarApart = 1, kFarAll = 2;
 

@@ -37,6 +37,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // (cell units, Eq. 3) and the squared top-hat radius b2 of the density estimate.
 struct PairConst {
   float c0, c1, c2, b2, g;
+  float near2;  // (1.1 eps)^2: beyond it the spline exceeds 1/r^3 by more than 1%
 };
 
 // One interaction: t += f(|d|) d with d = s - q (cell units) and r^2 taken with
@@ -68,6 +69,65 @@ __device__ __forceinline__ void interact(float sx, float sy, float sz, float qx,
   if (kDens) rho += __builtin_fmaxf(k.b2 - r2, 0.0f);
 }
 
+// kU interactions of one source group on a cell that may hold pairs inside
+// eps.  The separations are formed first; only if some lane has r^2 below
+// near2 = (1.1 eps)^2 (a wave-uniform vote) does the group take the spline
+// select, otherwise every pair is at least 1.1 eps apart, where the spline
+// exceeds 1/r^3 by over 1% and the minimum is exactly 1/r^3 -- so both ways
+// give the bits of interact<true>.
+template <int kU, bool kDens>
+__device__ __forceinline__ void interact_group_near(const float* c, float qx, float qy, float qz,
+                                                    const PairConst& k, float& tx, float& ty,
+                                                    float& tz, float& rho) {
+  float dx[kU], dy[kU], dz[kU], r2[kU];
+  float m = 3.0e38f;
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    dx[u] = c[3 * u] - qx;
+    dy[u] = c[3 * u + 1] - qy;
+    dz[u] = c[3 * u + 2] - qz;
+    r2[u] = __builtin_fmaf(dz[u], dz[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dx[u], dx[u], k.g)));
+    m = __builtin_fminf(m, r2[u]);
+  }
+  if (__ballot(m < k.near2) != 0) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const float rinv = rsq(r2[u]);
+      const float rinv3 = (rinv * rinv) * rinv;
+      const float r = r2[u] * rinv;
+      const float spline = __builtin_fmaf(__builtin_fmaf(k.c2, r, k.c1), r, k.c0);
+      const float f = __builtin_fminf(spline, rinv3);
+      tx = __builtin_fmaf(f, dx[u], tx);
+      ty = __builtin_fmaf(f, dy[u], ty);
+      tz = __builtin_fmaf(f, dz[u], tz);
+      if (kDens) rho += __builtin_fmaxf(k.b2 - r2[u], 0.0f);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const float rinv = rsq(r2[u]);
+      const float f = (rinv * rinv) * rinv;
+      tx = __builtin_fmaf(f, dx[u], tx);
+      ty = __builtin_fmaf(f, dy[u], ty);
+      tz = __builtin_fmaf(f, dz[u], tz);
+      if (kDens) rho += __builtin_fmaxf(k.b2 - r2[u], 0.0f);
+    }
+  }
+}
+
+template <int kU, bool kNear, bool kDens>
+__device__ __forceinline__ void interact_group(const float* c, float qx, float qy, float qz,
+                                               const PairConst& k, float& tx, float& ty,
+                                               float& tz, float& rho) {
+  if (kNear) {
+    interact_group_near<kU, kDens>(c, qx, qy, qz, k, tx, ty, tz, rho);
+  } else {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      interact<false, kDens>(c[3 * u], c[3 * u + 1], c[3 * u + 2], qx, qy, qz, k, tx, ty, tz, rho);
+  }
+}
+
 // Sum the sources [beg, end) into (tx, ty, tz) (and rho), kU per step.  Sources
 // are packed (x, y, z) records of 12 bytes so that a group of kU sources
 // occupies 3 kU SGPRs.  With kPipe the next kU sources are requested before the
@@ -86,27 +146,18 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ src3, int 
       float nxt[3 * kU];
 #pragma unroll
       for (int u = 0; u < 3 * kU; ++u) nxt[u] = src3[3 * (j + kU) + u];
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        interact<kNear, kDens>(cur[3 * u], cur[3 * u + 1], cur[3 * u + 2], qx, qy, qz, k, tx, ty,
-                               tz, rho);
+      interact_group<kU, kNear, kDens>(cur, qx, qy, qz, k, tx, ty, tz, rho);
 #pragma unroll
       for (int u = 0; u < 3 * kU; ++u) cur[u] = nxt[u];
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      interact<kNear, kDens>(cur[3 * u], cur[3 * u + 1], cur[3 * u + 2], qx, qy, qz, k, tx, ty, tz,
-                             rho);
+    interact_group<kU, kNear, kDens>(cur, qx, qy, qz, k, tx, ty, tz, rho);
     j += kU;
   }
   for (; j + kU <= end; j += kU) {
     float cur[3 * kU];
 #pragma unroll
     for (int u = 0; u < 3 * kU; ++u) cur[u] = src3[3 * j + u];
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      interact<kNear, kDens>(cur[3 * u], cur[3 * u + 1], cur[3 * u + 2], qx, qy, qz, k, tx, ty, tz,
-                             rho);
+    interact_group<kU, kNear, kDens>(cur, qx, qy, qz, k, tx, ty, tz, rho);
   }
   for (; j < end; ++j)
     interact<kNear, kDens>(src3[3 * j], src3[3 * j + 1], src3[3 * j + 2], qx, qy, qz, k, tx, ty,
@@ -158,6 +209,7 @@ __global__ __launch_bounds__(256) void k_pair_forward(
     kc.c2 = boxes[b].c2;
     kc.b2 = boxes[b].b2;
     kc.g = boxes[b].guard;
+    kc.near2 = boxes[b].near2;
     // c1 meets an SGPR operand (c2) in the spline FMA; a VALU instruction reads
     // at most one SGPR, so keep c1 in a VGPR for the whole item.
     asm volatile("" : "+v"(kc.c1));

@@ -64,7 +64,51 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 
 struct AdjConst {
   float c0, c1, c2, ha, hb, eps, g;
+  float near2;  // (1.1 eps)^2: beyond it every pair takes the Newton branch
 };
+
+// kU adjoint interactions of one source group on a cell that may hold pairs
+// inside eps: the separations come first, and only if some lane has r^2 below
+// (1.1 eps)^2 (a wave-uniform vote) does the group take the branch select;
+// otherwise every pair has r > eps and the Newton expressions give the same
+// bits as adjoint<true>.
+template <int kU>
+__device__ __forceinline__ void adjoint_group_near(const float* c, float qx, float qy, float qz,
+                                                   float wx, float wy, float wz,
+                                                   const AdjConst& k, float& gx, float& gy,
+                                                   float& gz) {
+  float m = 3.0e38f;
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const float dx = c[6 * u] - qx, dy = c[6 * u + 1] - qy, dz = c[6 * u + 2] - qz;
+    m = __builtin_fminf(m, __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, k.g))));
+  }
+  if (__ballot(m < k.near2) != 0) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      adjoint<true>(c + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
+                    gx, gy, gz);
+  } else {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      adjoint<false>(c + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
+                     gx, gy, gz);
+  }
+}
+
+template <int kU, bool kNear>
+__device__ __forceinline__ void adjoint_group(const float* c, float qx, float qy, float qz,
+                                              float wx, float wy, float wz, const AdjConst& k,
+                                              float& gx, float& gy, float& gz) {
+  if (kNear) {
+    adjoint_group_near<kU>(c, qx, qy, qz, wx, wy, wz, k, gx, gy, gz);
+  } else {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      adjoint<false>(c + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
+                     gx, gy, gz);
+  }
+}
 
 // Sum the sources [beg, end) of packed 24-byte records, kU per step (with kPipe
 // the next kU records are requested before the current ones are used).
@@ -82,27 +126,18 @@ __device__ __forceinline__ void sum_adjoint(const float* __restrict__ src6, int 
       float nxt[6 * kU];
 #pragma unroll
       for (int u = 0; u < 6 * kU; ++u) nxt[u] = src6[6 * (j + kU) + u];
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        adjoint<kNear>(cur + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
-                       gx, gy, gz);
+      adjoint_group<kU, kNear>(cur, qx, qy, qz, wx, wy, wz, k, gx, gy, gz);
 #pragma unroll
       for (int u = 0; u < 6 * kU; ++u) cur[u] = nxt[u];
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      adjoint<kNear>(cur + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, gx,
-                     gy, gz);
+    adjoint_group<kU, kNear>(cur, qx, qy, qz, wx, wy, wz, k, gx, gy, gz);
     j += kU;
   }
   for (; j + kU <= end; j += kU) {
     float cur[6 * kU];
 #pragma unroll
     for (int u = 0; u < 6 * kU; ++u) cur[u] = src6[6 * j + u];
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      adjoint<kNear>(cur + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, gx,
-                     gy, gz);
+    adjoint_group<kU, kNear>(cur, qx, qy, qz, wx, wy, wz, k, gx, gy, gz);
   }
   for (; j < end; ++j) {
     float one[6];
@@ -158,6 +193,7 @@ __global__ __launch_bounds__(256) void k_pair_vjp(
     AdjConst kc;
     kc.c0 = boxes[b].c0; kc.c1 = boxes[b].c1; kc.c2 = boxes[b].c2;
     kc.ha = boxes[b].ha; kc.hb = boxes[b].hb; kc.eps = boxes[b].eps; kc.g = boxes[b].guard;
+    kc.near2 = boxes[b].near2;
     // c1 and ha each meet another SGPR operand in an FMA; a VALU instruction
     // reads at most one SGPR, so keep them in VGPRs for the whole item.
     asm volatile("" : "+v"(kc.c1), "+v"(kc.ha));

@@ -76,7 +76,9 @@ __device__ __forceinline__ void sum64(const float* __restrict__ src3, int beg, i
     interact64<kNear>(src3[3 * j], src3[3 * j + 1], src3[3 * j + 2], qx, qy, qz, k, tx, ty, tz);
 }
 
-__global__ __launch_bounds__(256) void k_pair_forward_f64(
+// Capped at 64 VGPRs and 80 SGPRs (no spills) for 8 resident waves per SIMD
+// instead of the compiler's 7.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pair_forward_f64(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
     const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
     const int32_t* __restrict__ off, const float4* __restrict__ rel,

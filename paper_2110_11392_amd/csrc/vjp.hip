@@ -20,10 +20,15 @@ namespace anf {
 __device__ __forceinline__ float rsq_v(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // One adjoint interaction with the source record s = (x, y, z, w_x, w_y, w_z).
-// kNear: the pair may lie inside eps (select between spline and Newton); else
-// every pair of the source cell has r > eps and the Newton branch is exact.
-// Both paths evaluate the Newton branch with the same expressions, so a sink's
-// bits do not depend on which path a work item takes for a source cell.
+// The pair term f v + h (d.v) d is evaluated as F (v + T d) with F = f and
+// T = h (d.v) / f.  On the Newton branch T = -3 r^-2 (d.v), so no division is
+// needed there, and the form takes one instruction fewer than forming f v and
+// h (d.v) d separately.  Inside eps (kNear) the spline values select F = f and
+// T = h (d.v) / f, with f >= 0.625 / eps^3 > 0 (the spline's minimum).
+// kNear: the pair may lie inside eps; else every pair of the source cell has
+// r > eps and the Newton branch is exact.  Both paths evaluate the Newton
+// branch with the same expressions, so a sink's bits do not depend on which
+// path a work item takes for a source cell.
 template <bool kNear>
 __device__ __forceinline__ void adjoint(const float* s, float qx, float qy, float qz, float wx,
                                         float wy, float wz, float c0, float c1, float c2,
@@ -35,23 +40,26 @@ __device__ __forceinline__ void adjoint(const float* s, float qx, float qy, floa
   const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, g)));
   const float rinv = rsq_v(r2);
   const float rinv2 = rinv * rinv;
-  const float rinv3 = rinv2 * rinv;
-  float f = rinv3;
-  float h = (-3.0f * rinv2) * rinv3;
-  if (kNear) {
-    const float r = r2 * rinv;
-    const bool inner = r < eps;
-    f = inner ? __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0) : f;
-    h = inner ? __builtin_fmaf(hb, rinv, ha) : h;
-  }
   const float vx = s[3] - wx;
   const float vy = s[4] - wy;
   const float vz = s[5] - wz;
   const float dv = __builtin_fmaf(dz, vz, __builtin_fmaf(dy, vy, dx * vx));
-  const float k = h * dv;
-  gx = __builtin_fmaf(k, dx, __builtin_fmaf(f, vx, gx));
-  gy = __builtin_fmaf(k, dy, __builtin_fmaf(f, vy, gy));
-  gz = __builtin_fmaf(k, dz, __builtin_fmaf(f, vz, gz));
+  float F = rinv2 * rinv;
+  float T = (-3.0f * rinv2) * dv;
+  if (kNear) {
+    const float r = r2 * rinv;
+    const bool inner = r < eps;
+    const float fs = __builtin_fmaf(__builtin_fmaf(c2, r, c1), r, c0);
+    const float hs = __builtin_fmaf(hb, rinv, ha);
+    F = inner ? fs : F;
+    T = inner ? (hs * dv) * __builtin_amdgcn_rcpf(fs) : T;
+  }
+  const float ex = __builtin_fmaf(T, dx, vx);
+  const float ey = __builtin_fmaf(T, dy, vy);
+  const float ez = __builtin_fmaf(T, dz, vz);
+  gx = __builtin_fmaf(F, ex, gx);
+  gy = __builtin_fmaf(F, ey, gy);
+  gz = __builtin_fmaf(F, ez, gz);
 }
 
 __device__ __forceinline__ int wrap1_v(int v, int K) {
@@ -164,8 +172,16 @@ __global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ r
   src6[6 * s + 5] = w[3 * i + 2];
 }
 
+// Register caps for more resident waves: unroll 2 fits 8 waves per SIMD, unroll
+// 4 fits 7 with a few spills at x-offset-slice boundaries (none in the pair
+// loop).  Without the caps the compiler takes 112 SGPRs and, at unroll 4,
+// 80 VGPRs: 7 and 6 waves.
+template <int kU>
+constexpr int vjp_min_waves() { return kU <= 2 ? 8 : (kU == 4 ? 7 : 1); }
+
 template <int kAcc, int kU, bool kPipe>
-__global__ __launch_bounds__(256) void k_pair_vjp(
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
     const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
     const int32_t* __restrict__ off, const float* __restrict__ src6,

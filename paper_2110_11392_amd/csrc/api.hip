@@ -143,7 +143,8 @@ struct Layout {
   // binning region
   size_t counts, keys0, keys1, vals0, vals1, hist, hist_scan, bin_scan;
   // force / adjoint region (overlaps the binning region)
-  size_t pencil_counts, item_base, items, item_bucket, item_slot, tasks, ctrl, plan_scan, partial, mom,
+  size_t pencil_counts, item_base, items, item_bucket, item_slot, item_cost, tasks, ctrl, plan_scan,
+      partial, mom,
       src_w;
   size_t total;
   int64_t max_items, max_tasks, max_split;
@@ -178,6 +179,7 @@ Layout layout(const Resolved& r) {
   L.items = take(sizeof(int4) * (size_t)L.max_items);
   L.item_bucket = take(4 * (size_t)L.max_items);
   L.item_slot = take(4 * (size_t)L.max_items);
+  L.item_cost = take(4 * (size_t)L.max_items);
   L.max_split = r.split_slices > 1 ? std::min<int64_t>(kMaxSplit, L.max_items) : 0;
   L.max_tasks = plan_max_tasks(L.max_items, L.max_split);
   L.tasks = take(4 * (size_t)L.max_tasks);
@@ -300,6 +302,7 @@ PlanWork plan_work(void* ws, const Layout& L) {
   w.items = at<int4>(ws, L.items);
   w.item_bucket = at<int32_t>(ws, L.item_bucket);
   w.item_slot = at<int32_t>(ws, L.item_slot);
+  w.item_cost = at<int32_t>(ws, L.item_cost);
   w.tasks = at<int32_t>(ws, L.tasks);
   w.ctrl = at<int32_t>(ws, L.ctrl);
   w.partial = at<float>(ws, L.partial);

@@ -208,6 +208,23 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
                       const float* pos, const abacus_nf_binned* out, const BinWork& w,
                       hipStream_t s);
 
+// Wave priority from the work left in the wave's current task (sources still
+// to visit), so the SIMD's instruction arbiter favours the waves with the most
+// work left instead of the oldest waves.  With age order alone the last waves
+// dispatched to a SIMD barely advance while older ones run, and the heavy
+// first items they took finish long after the queue is empty.  `left` must be
+// wave-uniform.
+__device__ __forceinline__ void set_wave_priority(int left) {
+  if (left >= 8192)
+    __builtin_amdgcn_s_setprio(3);
+  else if (left >= 4096)
+    __builtin_amdgcn_s_setprio(2);
+  else if (left >= 2048)
+    __builtin_amdgcn_s_setprio(1);
+  else
+    __builtin_amdgcn_s_setprio(0);
+}
+
 // plan.hip
 struct PlanWork {
   int32_t* pencil_counts;  // pencils_total
@@ -215,6 +232,7 @@ struct PlanWork {
   int4* items;             // max_items
   int32_t* item_bucket;    // max_items: cost bucket of each item
   int32_t* item_slot;      // max_items: position of the item inside its bucket
+  int32_t* item_cost;      // max_items: sources the item's wave visits (all x offsets)
   int32_t* tasks;          // max_tasks: item << kTaskShift | code, longest first
   int32_t* ctrl;           // kCtrlInts
   int32_t* scan_tmp;

@@ -186,7 +186,7 @@ template <int kAcc, bool kCount, int kU, bool kPipe, bool kDens>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void k_pair_forward(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
-    const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
+    const int32_t* __restrict__ tasks, const int32_t* __restrict__ item_cost, int32_t* __restrict__ ctrl,
     const int32_t* __restrict__ off, const float4* __restrict__ rel,
     const float* __restrict__ src3, const int32_t* __restrict__ perm, float* __restrict__ acc_out,
     float* __restrict__ dens_out, float* __restrict__ partial,
@@ -210,6 +210,10 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
     const int za = uniform(it.z & 0xffff), zb = uniform(it.z >> 16);
     const int first = uniform(it.w);
     const int K = uniform(boxes[b].K), R = uniform(boxes[b].R);
+    // sources this task visits: the item's cost, or one x offset's share of it
+    int left = uniform(item_cost[task >> kTaskShift]);
+    if (code) left /= 2 * R + 1;
+    set_wave_priority(left);
     const int cbase = uniform(boxes[b].cell_base);
     PairConst kc;
     kc.c0 = boxes[b].c0;
@@ -258,6 +262,8 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
           const int sz = wrap1(zu, K);
           const int beg = uniform(off[col + sz]), end = uniform(off[col + sz + 1]);
           if (beg == end) continue;
+          left -= end - beg;
+          set_wave_priority(left);
           const int oz = zu - lane_z;
           // Wave-uniform: is this source cell within one cell of every sink
           // cell of the item, and can a pair of it fall inside the spline?
@@ -340,7 +346,7 @@ static hipError_t launch_forward_t(const DevBox* boxes, const PlanWork& w, const
   const void* fn = reinterpret_cast<const void*>(&k_pair_forward<kAcc, kCount, kU, kPipe, kDens>);
   const int blocks = persistent_blocks(fn, 256) * grid_mult;
   hipLaunchKernelGGL((k_pair_forward<kAcc, kCount, kU, kPipe, kDens>), dim3(blocks), dim3(256), 0,
-                     s, boxes, w.items, w.tasks, w.ctrl, off, reinterpret_cast<const float4*>(rel),
+                     s, boxes, w.items, w.tasks, w.item_cost, w.ctrl, off, reinterpret_cast<const float4*>(rel),
                      src3, perm, acc, dens, w.partial,
                      reinterpret_cast<unsigned long long*>(pair_count));
   return hipGetLastError();

@@ -80,7 +80,8 @@ __device__ __forceinline__ void sum64(const float* __restrict__ src3, int beg, i
 // instead of the compiler's 7.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pair_forward_f64(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
-    const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
+    const int32_t* __restrict__ tasks, const int32_t* __restrict__ item_cost,
+    int32_t* __restrict__ ctrl,
     const int32_t* __restrict__ off, const float4* __restrict__ rel,
     const float* __restrict__ src3, const int32_t* __restrict__ perm,
     double* __restrict__ acc_out) {
@@ -90,7 +91,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
     t = uni64(__shfl(t, 0, 64));
     if (t >= n_tasks) break;
-    const int4 it = items[uni64(tasks[t]) >> kTaskShift];
+    const int item = uni64(tasks[t]) >> kTaskShift;
+    const int4 it = items[item];
+    int left = uni64(item_cost[item]);
+    set_wave_priority(left);
     const int b = uni64(it.x & 0xffff), count = uni64(it.x >> 16);
     const int cx = uni64(it.y & 0xffff), cy = uni64(it.y >> 16);
     const int za = uni64(it.z & 0xffff), zb = uni64(it.z >> 16);
@@ -128,6 +132,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
           const int sz = wrap64(zu, K);
           const int beg = uni64(off[col + sz]), end = uni64(off[col + sz + 1]);
           if (beg == end) continue;
+          left -= end - beg;
+          set_wave_priority(left);
           const int oz = zu - lane_z;
           const bool near = far_mode == kFarNone ||
                             (far_mode == kFarApart && col_near && zu >= za - 1 && zu <= zb + 1);
@@ -173,7 +179,7 @@ hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int3
   const void* fn = reinterpret_cast<const void*>(&k_pair_forward_f64);
   const int blocks = persistent_blocks(fn, 256);
   hipLaunchKernelGGL(k_pair_forward_f64, dim3(blocks), dim3(256), 0, s, boxes, w.items, w.tasks,
-                     w.ctrl, off, reinterpret_cast<const float4*>(rel), src3, perm, acc);
+                     w.item_cost, w.ctrl, off, reinterpret_cast<const float4*>(rel), src3, perm, acc);
   return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
                                                    const int32_t* __restrict__ off,
                                                    int32_t* __restrict__ bucket_of,
                                                    int32_t* __restrict__ slot_of,
+                                                   int32_t* __restrict__ cost_of,
                                                    int32_t* __restrict__ bucket_count) {
   __shared__ int local[kBuckets];
   __shared__ int base[kBuckets];
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
       }
     }
     const int lg = cost > 0 ? 63 - __clzll((unsigned long long)cost) : 0;
+    cost_of[q] = cost < 0x7fffffff ? (int32_t)cost : 0x7fffffff;
     bucket = kBuckets - 1 - lg;
     rank = atomicAdd(&local[bucket], 1);  // LDS atomic: cheap, order irrelevant
   }
@@ -250,7 +252,7 @@ hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils, const i
   const int32_t* n_items = w.item_base + pencils;
   const unsigned gi = (unsigned)((w.max_items + 255) / 256);
   hipLaunchKernelGGL(k_item_cost, dim3(gi), dim3(256), 0, s, boxes, w.items, n_items, off,
-                     w.item_bucket, w.item_slot, w.ctrl);
+                     w.item_bucket, w.item_slot, w.item_cost, w.ctrl);
   ANF_TRY(hipGetLastError());
   const int split = (int)(w.split_items < w.max_split ? w.split_items : w.max_split);
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, s, w.ctrl, n_items,

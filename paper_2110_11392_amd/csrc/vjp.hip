@@ -183,8 +183,8 @@ template <int kAcc, int kU, bool kPipe>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
-    const int32_t* __restrict__ tasks, int32_t* __restrict__ ctrl,
-    const int32_t* __restrict__ off, const float* __restrict__ src6,
+    const int32_t* __restrict__ tasks, const int32_t* __restrict__ item_cost,
+    int32_t* __restrict__ ctrl, const int32_t* __restrict__ off, const float* __restrict__ src6,
     const int32_t* __restrict__ perm, float* __restrict__ grad, float* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
   const int n_tasks = uni(ctrl[kCtrlNTasks]);
@@ -205,6 +205,10 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     const int za = uni(it.z & 0xffff), zb = uni(it.z >> 16);
     const int first = uni(it.w);
     const int K = uni(boxes[b].K), R = uni(boxes[b].R);
+    // sources this task visits: the item's cost, or one x offset's share of it
+    int left = uni(item_cost[task >> kTaskShift]);
+    if (code) left /= 2 * R + 1;
+    set_wave_priority(left);
     const int cbase = uni(boxes[b].cell_base);
     AdjConst kc;
     kc.c0 = boxes[b].c0; kc.c1 = boxes[b].c1; kc.c2 = boxes[b].c2;
@@ -251,6 +255,8 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
           const int sz = wrap1_v(zu, K);
           const int beg = uni(off[col + sz]), end = uni(off[col + sz + 1]);
           if (beg == end) continue;
+          left -= end - beg;
+          set_wave_priority(left);
           const int oz = zu - lane_z;
           const bool near = far_mode == kFarNone ||
                             (far_mode == kFarApart && col_near && zu >= za - 1 && zu <= zb + 1);
@@ -319,7 +325,7 @@ static hipError_t launch_vjp_t(const DevBox* boxes, const PlanWork& w, const int
   const void* fn = reinterpret_cast<const void*>(&k_pair_vjp<kAcc, kU, kPipe>);
   const int blocks = persistent_blocks(fn, 256) * grid_mult;
   hipLaunchKernelGGL((k_pair_vjp<kAcc, kU, kPipe>), dim3(blocks), dim3(256), 0, s, boxes, w.items,
-                     w.tasks, w.ctrl, off, src, perm, grad, w.partial);
+                     w.tasks, w.item_cost, w.ctrl, off, src, perm, grad, w.partial);
   return hipGetLastError();
 }
 

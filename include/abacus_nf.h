@@ -109,7 +109,9 @@ typedef struct {
 /* ---- entry points ------------------------------------------------------- */
 
 /* Totals of a box list: *n_total = sum n, *cells_total = sum K^3.
- * EINVAL on a bad box, ERANGE if either total reaches 2^31. */
+ * EINVAL on a bad box, ERANGE if either total reaches 2^31 or the pair
+ * kernels' work plan could exceed 2^28 items (n/64 + cells + 2 K^2 summed
+ * over the boxes reaches 2^28, i.e. more than about 2.7e8 cells). */
 int abacus_nf_layout(const abacus_nf_box *boxes, int nboxes, int64_t *n_total,
                      int64_t *cells_total);
 

@@ -128,6 +128,9 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = f
   for (int b = 1; b < nboxes; ++b)
     if (in[b].radius != in[0].radius) split_slices = 1;
   out->split_slices = split_slices <= kMaxSlices ? split_slices : 1;
+  // Work items are queued as item << kTaskShift | code in an int32.
+  if (plan_max_items(n_total, cells_total, pencils_total) >= ((int64_t)1 << (31 - kTaskShift)))
+    return ABACUS_NF_ERANGE;
   out->n_total = n_total;
   out->cells_total = cells_total;
   out->pencils_total = pencils_total;

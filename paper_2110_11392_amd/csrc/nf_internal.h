@@ -20,8 +20,10 @@ constexpr int kChunk = 64;
 // span parameter is 1..kMaxSpan; kDefaultSpan unless the autotuner chose another).
 constexpr int kMaxSpan = 3;
 constexpr int kDefaultSpan = 2;
-// Cost buckets for the longest-first work queue (floor(log2 cost) descending).
-constexpr int kBuckets = 64;
+// Cost buckets for the longest-first work queue, descending: four per octave
+// (floor(log2 cost) and the next two bits of the cost), so the queue's order
+// is within 19% of exact longest-first.
+constexpr int kBuckets = 128;
 // ctrl layout (int32): bucket counts [kBuckets], bucket bases [kBuckets], then
 // the task head, task count, whole-item tasks, split items and slices per item.
 constexpr int kCtrlHead = 2 * kBuckets;

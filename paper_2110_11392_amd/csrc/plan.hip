@@ -9,7 +9,7 @@
 // chunk spanning two cells costs one extra z-layer of source cells but keeps
 // all 64 lanes busy where cells hold fewer than 64 particles.
 //
-// Items are queued longest first (bucketed by floor(log2 cost), cost = number
+// Items are queued longest first (bucketed by quarter octaves of cost, cost = number
 // of sources the wave visits) so the persistent grid drains evenly; the
 // cheapest items at the end are split into one task per x offset so the last
 // tasks are short and the grid's tail shrinks.
@@ -117,7 +117,9 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
     }
     const int lg = cost > 0 ? 63 - __clzll((unsigned long long)cost) : 0;
     cost_of[q] = cost < 0x7fffffff ? (int32_t)cost : 0x7fffffff;
-    bucket = kBuckets - 1 - lg;
+    const int quarter = lg >= 2 ? (int)((cost >> (lg - 2)) & 3) : 0;
+    const int key = 4 * lg + quarter;  // costs reach 25 * 2^31 at most: clamp to the last bucket
+    bucket = kBuckets - 1 - (key < kBuckets - 1 ? key : kBuckets - 1);
     rank = atomicAdd(&local[bucket], 1);  // LDS atomic: cheap, order irrelevant
   }
   __syncthreads();

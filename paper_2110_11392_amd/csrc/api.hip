@@ -629,7 +629,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
 // ---- cell multipoles ---------------------------------------------------------
 
 struct MpLayout {
-  size_t boxtab, keys, hist, base, cursor, waves, sorted, full, total;
+  size_t boxtab, keys, hist, base, cursor, waves, sorted, span, full, total;
 };
 
 MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
@@ -647,6 +647,7 @@ MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
   L.cursor = take(4 * (size_t)kMpBuckets);
   L.waves = take(4 * (size_t)kMpBuckets);
   L.sorted = take(4 * (size_t)r.cells_total);
+  L.span = take(8 * (size_t)r.cells_total);
   L.full = reduced ? take(sizeof(double) * (size_t)multipole_terms(order, false) *
                           (size_t)r.cells_total)
                    : 0;
@@ -740,6 +741,7 @@ int abacus_nf_multipoles(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   w.cursor = at<int32_t>(ws, L.cursor);
   w.bucket_waves = at<int32_t>(ws, L.waves);
   w.sorted = at<int32_t>(ws, L.sorted);
+  w.span = at<int2>(ws, L.span);
   w.full = reduced ? at<double>(ws, L.full) : nullptr;
   Timer t(4, s);
   ANF_HIP(launch_multipoles(dboxes, nboxes, r.cells_total, order, reduced, w, b->cell_offsets,

@@ -29,10 +29,16 @@
 namespace anf {
 
 constexpr int kMpSeg = 16;     // target particles per lane
-constexpr int kMpStage = 64 * kMpSeg;  // particles a wave stages in LDS
-// Buckets: (log2 L, per) for per <= kMpSeg, then one bucket of cells that need
-// 64 lanes and more than kMpSeg particles per lane, then the empty cells.
-constexpr int kMpGiant = 7 * (kMpSeg + 1);
+constexpr bool kMpUseLds = true;  // stage each wave's offsets in LDS
+constexpr int kMpStage = kMpUseLds ? 64 * kMpSeg : 1;  // particles a wave stages in LDS
+// Buckets: (log2 L, ceil(per / kMpPerStep)) for per <= kMpSeg, then one bucket
+// of cells that need 64 lanes and more than kMpSeg particles per lane, then
+// the empty cells.
+constexpr int kMpPerLevels = 16;
+constexpr int kMpPerStep = kMpSeg / kMpPerLevels;
+static_assert(kMpSeg % kMpPerLevels == 0, "per-lane levels");
+static_assert(!kMpUseLds || kMpPerStep == 1, "LDS staging needs the exact per-lane count");
+constexpr int kMpGiant = 7 * (kMpPerLevels + 1);
 constexpr int kMpEmpty = kMpGiant + 1;
 static_assert(kMpEmpty + 2 <= kMpBuckets && kMpEmpty + 2 <= 256, "bucket arrays and scan");
 
@@ -44,9 +50,9 @@ __host__ __device__ constexpr int mp_terms_a(int p, int a0, int a1) {
 
 // Passes over a lane's particles: the terms are split by the power of x into
 // consecutive ranges of at most mp_max_acc terms (greedy), so the partial sums
-// of one pass fit in VGPRs with room for three waves per SIMD (p = 8: 45 + 64
-// + 56 terms in three passes).
-__host__ __device__ constexpr int mp_max_acc(int p) { return p < 0 ? 0 : 64; }
+// of one pass fit in VGPRs with room for three waves per SIMD and no spills
+// (p = 8: 45 + 36 + 49 + 35 terms in four passes).
+__host__ __device__ constexpr int mp_max_acc(int p) { return p < 0 ? 0 : 56; }
 
 // First power of x of pass `k` (pass k covers [mp_pass_a0(p, k), mp_pass_a0(p, k+1) - 1]);
 // p + 1 once the passes are exhausted.
@@ -80,12 +86,12 @@ __device__ __forceinline__ int mp_key(int n) {
   if (n <= 0) return kMpEmpty;
   const int l = mp_lanes_log2(n);
   const int per = (n + (1 << l) - 1) >> l;
-  return per <= kMpSeg ? l * (kMpSeg + 1) + per : kMpGiant;
+  return per <= kMpSeg ? l * (kMpPerLevels + 1) + (per + kMpPerStep - 1) / kMpPerStep : kMpGiant;
 }
 
 // Lanes per cell of a bucket (the giant and empty buckets: 64 and 1).
 __host__ __device__ constexpr int mp_key_lanes_log2(int key) {
-  return key == kMpGiant ? 6 : (key == kMpEmpty ? 0 : key / (kMpSeg + 1));
+  return key == kMpGiant ? 6 : (key == kMpEmpty ? 0 : key / (kMpPerLevels + 1));
 }
 
 // ---- planning: counting sort of the cells by bucket --------------------------
@@ -140,8 +146,10 @@ __global__ __launch_bounds__(256) void k_mp_buckets(const int32_t* __restrict__ 
 // bucket with a single global atomic (the order inside a bucket does not
 // matter: every cell's sums are independent of its position).
 __global__ __launch_bounds__(256) void k_mp_scatter(const int32_t* __restrict__ key_in,
+                                                    const int32_t* __restrict__ off,
                                                     int64_t cells, int32_t* __restrict__ cursor,
-                                                    int32_t* __restrict__ sorted) {
+                                                    int32_t* __restrict__ sorted,
+                                                    int2* __restrict__ span) {
   __shared__ int cnt[kMpEmpty + 1], start[kMpEmpty + 1];
   for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x) cnt[k] = 0;
   __syncthreads();
@@ -155,7 +163,11 @@ __global__ __launch_bounds__(256) void k_mp_scatter(const int32_t* __restrict__ 
   for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x)
     start[k] = cnt[k] ? atomicAdd(&cursor[k], cnt[k]) : 0;
   __syncthreads();
-  if (key >= 0) sorted[start[key] + rank] = (int32_t)c;
+  if (key >= 0) {
+    const int at = start[key] + rank;
+    sorted[at] = (int32_t)c;
+    span[at] = make_int2(off[c], off[c + 1] - off[c]);
+  }
 }
 
 // ---- the moment kernel ----------------------------------------------------
@@ -190,6 +202,23 @@ __device__ __forceinline__ void mp_add(const float4 r, double (&acc)[T]) {
     }
     xa *= x;
   }
+}
+
+// One DPP move of a double (two 32-bit halves).  With every row enabled each
+// lane reads its source lane; with a partial row mask the lanes of the other
+// rows read 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double mp_dpp(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  int lo, hi;
+  if constexpr (kRowMask == 0xF) {
+    lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, kCtrl, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), kCtrl, 0xF, 0xF, true);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, kCtrl, kRowMask, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), kCtrl, kRowMask, 0xF, false);
+  }
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // A lane's share of its wave: particles [beg, end) of global cell `cell`
@@ -236,12 +265,27 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
       __builtin_amdgcn_sched_barrier(0);
     }
   };
-  if (ln.lds >= 0) {
+  if (kMpUseLds && ln.lds >= 0) {
+    // The next particle's offsets are read from LDS before this particle's
+    // terms are added, so the LDS latency hides behind the arithmetic.
     const int cnt = end - beg;
     const float* sx = sh.x + ln.lds;
     const float* sy = sh.y + ln.lds;
     const float* sz = sh.z + ln.lds;
-    for (int m = 0; m < cnt; ++m) mp_add<P, A0, A1>(make_float4(sx[m], sy[m], sz[m], 0.f), acc);
+    if (cnt > 0) {
+      // particle m of this lane's segment sits in row m: sx[64 m]
+      float nx = sx[0], ny = sy[0], nz = sz[0];
+      for (int m = 0; m < cnt; ++m) {
+        const float4 cur = make_float4(nx, ny, nz, 0.f);
+        const int k = m + 1 < cnt ? m + 1 : m;
+        nx = sx[64 * k];
+        ny = sy[64 * k];
+        nz = sz[64 * k];
+        __builtin_amdgcn_sched_barrier(0);
+        mp_add<P, A0, A1>(cur, acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
   } else {
   int j = beg;
   if (j + kG <= end) {
@@ -261,15 +305,39 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
   }
   for (; j < end; ++j) mp_add<P, A0, A1>(rel[j], acc);
   }
-  // Add each cell's L lanes in registers with a butterfly over its aligned
-  // block (lane i takes lane i ^ h for h = 1, 2, ..., L/2: a fixed pairwise
-  // order), then the block's first lane scales by w^(a+b+c) and writes the
-  // row.  An empty cell's lane writes zeros.
-  for (int h = 1; h < ln.n; h <<= 1) {
+  // Add each cell's L lanes in registers over its aligned block of lanes with
+  // DPP moves (no LDS round trips): partner lane i^1, then i^2 (quad
+  // permutes), the mirrored half-row and the mirrored row, after which every
+  // lane of a block of up to 16 holds the block's sum; for 32 and 64 lanes the
+  // row broadcasts add rows 0 and 2 into rows 1 and 3, then rows 0-1 into rows
+  // 2-3.  The block's last lane then holds the sum in a fixed order (a + b and
+  // b + a round alike, so all holders agree), scales it by w^(a+b+c) and
+  // writes the row.  An empty cell's lane writes zeros.
+  if (depth >= 1) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += __shfl_xor(acc[t], h, 64);
+    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0xB1, 0xF>(acc[t]);   // quad_perm [1,0,3,2]
   }
-  if (ln.cell >= 0 && ln.i == 0) {
+  if (depth >= 2) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x4E, 0xF>(acc[t]);   // quad_perm [2,3,0,1]
+  }
+  if (depth >= 3) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x141, 0xF>(acc[t]);  // row_half_mirror
+  }
+  if (depth >= 4) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x140, 0xF>(acc[t]);  // row_mirror
+  }
+  if (depth >= 5) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x142, 0xA>(acc[t]);  // row_bcast:15 -> rows 1, 3
+  }
+  if (depth >= 6) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x143, 0xC>(acc[t]);  // row_bcast:31 -> rows 2, 3
+  }
+  if (ln.cell >= 0 && ln.i == ln.n - 1) {
     double* dst = out + (int64_t)ln.cell * TT + base;
     double wp[P + 1];
     wp[0] = 1.0;
@@ -289,87 +357,98 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
 }
 
 template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_multipoles(const DevBox* __restrict__ boxes, int nboxes,
-                                                   const int32_t* __restrict__ bucket_base,
-                                                   const int32_t* __restrict__ bucket_waves,
-                                                   const int32_t* __restrict__ sorted,
-                                                   const int32_t* __restrict__ off,
-                                                   const float4* __restrict__ rel,
-                                                   double* __restrict__ out) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_multipoles(
+    const DevBox* __restrict__ boxes, int nboxes, const int32_t* __restrict__ bucket_base,
+    const int32_t* __restrict__ bucket_waves, const int32_t* __restrict__ sorted,
+    const int2* __restrict__ span, const float4* __restrict__ rel, double* __restrict__ out) {
   __shared__ MpShared sh;
   constexpr int S1 = mp_pass_a0(P, 1), S2 = mp_pass_a0(P, 2), S3 = mp_pass_a0(P, 3);
   static_assert(mp_pass_a0(P, 4) > P, "at most four passes");
   static_assert(P <= 8, "order table sized for p <= 8");
   const int lane = threadIdx.x;
   const int n_waves = __builtin_amdgcn_readfirstlane(bucket_waves[kMpEmpty + 1]);
-  for (int wv = blockIdx.x; wv < n_waves; wv += gridDim.x) {
-    // the bucket of this wave: the last k with bucket_waves[k] <= wv
-    int lo = 0, hi = kMpEmpty;
+  // A work wave takes the sorted cells [first, first + ncell) of one bucket;
+  // lane k < ncell holds cell k's id and (first particle, count).  The next
+  // work wave's cells are requested before this one's arithmetic, so their
+  // memory latency overlaps it.
+  int key = 0, ncell = 0, my_c = -1;
+  int2 my_sp = make_int2(0, 0);
+  auto fetch = [&](int wv) {
+    int lo = 0, hi = kMpEmpty;  // the bucket of wave wv: the last k with bucket_waves[k] <= wv
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (__builtin_amdgcn_readfirstlane(bucket_waves[mid]) <= wv) lo = mid; else hi = mid - 1;
     }
-    const int key = lo;
-    const int l2 = mp_key_lanes_log2(key);
+    key = lo;
+    const int per_wave = 64 >> mp_key_lanes_log2(key);
+    const int first = __builtin_amdgcn_readfirstlane(bucket_base[key]) +
+                      (wv - __builtin_amdgcn_readfirstlane(bucket_waves[key])) * per_wave;
+    const int lim = __builtin_amdgcn_readfirstlane(bucket_base[key + 1]);
+    ncell = lim - first < per_wave ? lim - first : per_wave;
+    my_c = -1;
+    my_sp = make_int2(0, 0);
+    if (lane < ncell) {
+      my_c = sorted[first + lane];
+      my_sp = span[first + lane];
+    }
+  };
+  if ((int)blockIdx.x < n_waves) fetch(blockIdx.x);
+  for (int wv = blockIdx.x; wv < n_waves; wv += gridDim.x) {
+    const int cur_key = key, cur_ncell = ncell, cur_c = my_c;
+    const int2 cur_sp = my_sp;
+    if (wv + (int)gridDim.x < n_waves) fetch(wv + gridDim.x);
+    const int l2 = mp_key_lanes_log2(cur_key);
     const int L = 1 << l2;
-    const int idx = __builtin_amdgcn_readfirstlane(bucket_base[key]) +
-                    (wv - __builtin_amdgcn_readfirstlane(bucket_waves[key])) * (64 >> l2) +
-                    (lane >> l2);
+    const int k = lane >> l2;  // this lane's cell within the wave
+    const int c = __shfl(cur_c, k, 64);
+    const int cb = __shfl(cur_sp.x, k, 64), cn = __shfl(cur_sp.y, k, 64);
     MpLane ln = {0, 0, -1, lane & (L - 1), L, -1, 0.0};
-    if (idx < bucket_base[key + 1]) {
-      const int c = sorted[idx];
-      const int cb = off[c], ce = off[c + 1];
-      const int per = (ce - cb + L - 1) >> l2;
+    if (k < cur_ncell) {
+      const int per = (cn + L - 1) >> l2;
+      const int ce = cb + cn;
       ln.beg = cb + ln.i * per < ce ? cb + ln.i * per : ce;
       ln.end = ln.beg + per < ce ? ln.beg + per : ce;
       ln.cell = c;
       const int b = nboxes == 1 ? 0 : find_box_by_cell(boxes, nboxes, c);
       ln.w = boxes[b].width;
     }
-    if (key < kMpGiant) {
-      // Stage the wave's cells: cell k of the wave owns slots
-      // [k L per, (k + 1) L per), its lanes read their segments from there.
-      const int per = key - l2 * (kMpSeg + 1);
-      const int first = __builtin_amdgcn_readfirstlane(bucket_base[key]) +
-                        (wv - __builtin_amdgcn_readfirstlane(bucket_waves[key])) * (64 >> l2);
-      const int lim = __builtin_amdgcn_readfirstlane(bucket_base[key + 1]);
-      // lane k fetches the bounds of the wave's cell k, all at once
-      int my_cb = 0, my_n = 0;
-      if (lane < (64 >> l2) && first + lane < lim) {
-        const int c = sorted[first + lane];
-        my_cb = off[c];
-        my_n = off[c + 1] - my_cb;
+    if (kMpUseLds && cur_key < kMpGiant) {
+      // Stage the wave's cells in LDS, one row of 64 slots per particle index
+      // within a segment: particle m of cell k belongs to segment lane
+      // k L + m / per, row m % per, slot 64 row + lane, so a lane's reads in
+      // the passes walk one column and the 64 lanes read 64 consecutive
+      // words (no bank conflicts).  Particle slot + 64 j of the wave's cells
+      // (in cell order, cell k starting at k L per) is fetched by lane `lane`
+      // in step j; all steps' loads are in flight together.
+      const int per = cur_key - l2 * (kMpPerLevels + 1);
+      const int stride = L * per;
+      // Straight-line code: every step loads (slots past the wave's cells
+      // re-read the wave's first particle) and only real slots are stored.
+      const int safe = __shfl(cur_sp.x, 0, 64);
+      float4 r[kMpSeg];
+      int dst[kMpSeg];
+      int slot_ok = 0;
+#pragma unroll
+      for (int j = 0; j < kMpSeg; ++j) {
+        const int slot = lane + 64 * j;
+        const int kk = slot / stride;
+        const int m = slot - kk * stride;
+        const int cbk = __shfl(cur_sp.x, kk & 63, 64), nk = __shfl(cur_sp.y, kk & 63, 64);
+        const bool ok = j < per && kk < cur_ncell && m < nk;
+        r[j] = rel[ok ? cbk + m : safe];
+        const int q = m / per;
+        dst[j] = 64 * (m - q * per) + kk * L + q;
+        slot_ok |= ok ? 1 << j : 0;
       }
-      const int ncell = (lim - first) < (64 >> l2) ? (lim - first) : (64 >> l2);
-      // Four cells at a time: their first 64 particles are requested together
-      // so one memory latency covers four cells; longer cells finish after.
-      for (int k = 0; k < ncell; k += 4) {
-        float4 r[4];
-        int cbs[4], ns[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const bool ok = k + u < ncell;
-          cbs[u] = ok ? __builtin_amdgcn_readlane(my_cb, (k + u) & 63) : 0;
-          ns[u] = ok ? __builtin_amdgcn_readlane(my_n, (k + u) & 63) : 0;
-          if (lane < ns[u]) r[u] = rel[cbs[u] + lane];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int slot = (k + u) * L * per;
-          if (lane < ns[u]) {
-            sh.x[slot + lane] = r[u].x;
-            sh.y[slot + lane] = r[u].y;
-            sh.z[slot + lane] = r[u].z;
-          }
-          for (int m = lane + 64; m < ns[u]; m += 64) {
-            const float4 q = rel[cbs[u] + m];
-            sh.x[slot + m] = q.x;
-            sh.y[slot + m] = q.y;
-            sh.z[slot + m] = q.z;
-          }
+      for (int j = 0; j < kMpSeg; ++j) {
+        if (slot_ok & (1 << j)) {
+          sh.x[dst[j]] = r[j].x;
+          sh.y[dst[j]] = r[j].y;
+          sh.z[dst[j]] = r[j].z;
         }
       }
-      if (ln.cell >= 0) ln.lds = (lane >> l2) * L * per + ln.i * per;
+      if (ln.cell >= 0) ln.lds = lane;
     }
     __syncthreads();
     mp_pass<P, 0, S1 - 1>(rel, ln, sh, lane, l2, out);
@@ -460,11 +539,12 @@ __global__ __launch_bounds__(256) void k_mp_reduce(const double* __restrict__ fu
 template <int P>
 static hipError_t launch_mp_t(const DevBox* boxes, int nboxes, const MpWork& w,
                               const int32_t* off, const float* rel, double* full, hipStream_t s) {
+  (void)off;  // the cells' particle ranges come from the planner's span table
   const void* fn = reinterpret_cast<const void*>(&k_multipoles<P>);
   int blocks = persistent_blocks(fn, 64);
   if ((int64_t)blocks > w.cells) blocks = (int)(w.cells > 0 ? w.cells : 1);
   hipLaunchKernelGGL(k_multipoles<P>, dim3(blocks), dim3(64), 0, s, boxes, nboxes, w.bucket_base,
-                     w.bucket_waves, w.sorted, off, reinterpret_cast<const float4*>(rel), full);
+                     w.bucket_waves, w.sorted, w.span, reinterpret_cast<const float4*>(rel), full);
   return hipGetLastError();
 }
 
@@ -480,8 +560,8 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
   hipLaunchKernelGGL(k_mp_buckets, dim3(1), dim3(256), 0, s, w.hist, w.bucket_base, w.cursor,
                      w.bucket_waves);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mp_scatter, dim3(cg), dim3(256), 0, s, w.keys, cells_total, w.cursor,
-                     w.sorted);
+  hipLaunchKernelGGL(k_mp_scatter, dim3(cg), dim3(256), 0, s, w.keys, off, cells_total, w.cursor,
+                     w.sorted, w.span);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   double* full = reduced ? w.full : out;
   switch (order) {

@@ -176,6 +176,7 @@ struct MpWork {
   int32_t* cursor;        // kMpBuckets: scatter cursors
   int32_t* bucket_waves;  // kMpBuckets: first work wave of each bucket (+ total)
   int32_t* sorted;        // cells: cell ids sorted by bucket
+  int2* span;             // cells: (first particle, count) of each sorted cell
   double* full;           // cells_total x complete terms (only for the reduced basis)
 };
 int64_t multipole_terms(int p, bool reduced);

@@ -12,8 +12,8 @@
 // so the layout of the traffic is what matters.  One wave per cell (a
 // persistent loop over cells): lanes stride over the cell's sorted slots and
 // gather the particle through the permutation, so every lane of a cell adds to
-// the same statistics and the wave reduces them with a fixed butterfly -- no
-// atomics, and run-to-run identical results.  When the caller keeps particles
+// the same statistics and the wave reduces them with DPP moves in a fixed
+// order -- no atomics, and run-to-run identical results.  When the caller keeps particles
 // in cell order (as the slabs of the paper's code do), the gathers are
 // contiguous.  The per-box statistics are a two-level, fixed-order reduction
 // over chunks of 512 cells.
@@ -56,9 +56,19 @@ __global__ __launch_bounds__(256) void k_kick_drift(const DevBox* __restrict__ b
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  // The next cell's slot range is requested before this cell's particles are
+  // processed, so its latency overlaps them.
+  int nbeg = 0, nend = 0;
+  if (wave < cells_total) {
+    nbeg = __builtin_amdgcn_readfirstlane(off[wave]);
+    nend = __builtin_amdgcn_readfirstlane(off[wave + 1]);
+  }
   for (int64_t c = wave; c < cells_total; c += nwaves) {
-    const int beg = __builtin_amdgcn_readfirstlane(off[c]);
-    const int end = __builtin_amdgcn_readfirstlane(off[c + 1]);
+    const int beg = nbeg, end = nend;
+    if (c + nwaves < cells_total) {
+      nbeg = __builtin_amdgcn_readfirstlane(off[c + nwaves]);
+      nend = __builtin_amdgcn_readfirstlane(off[c + nwaves + 1]);
+    }
     const int b = nboxes == 1 ? 0 : find_box_by_cell(boxes, nboxes, c);
     const double kick = boxes[b].kick, drift = boxes[b].drift, L = boxes[b].box_len;
     double s2 = 0.0, am = 0.0;
@@ -79,12 +89,20 @@ __global__ __launch_bounds__(256) void k_kick_drift(const DevBox* __restrict__ b
       const double a = sqrt(a2);
       am = a > am ? a : am;
     }
-    for (int d = 32; d >= 1; d >>= 1) {
-      s2 += __shfl_xor(s2, d, 64);
-      const double o = __shfl_xor(am, d, 64);
-      am = o > am ? o : am;
+    // Sum and maximum over the wave with DPP moves in a fixed pattern (quad
+    // permutes, half-row and row mirrors, then the row broadcasts into rows 1
+    // and 3 and into rows 2 and 3); lane 63 ends with both totals.  Lanes of
+    // rows a broadcast does not write add 0, and 0 <= |a| leaves the maximum.
+    {
+      double o;
+      o = dpp_f64<0xB1, 0xF>(s2); s2 += o; o = dpp_f64<0xB1, 0xF>(am); am = o > am ? o : am;
+      o = dpp_f64<0x4E, 0xF>(s2); s2 += o; o = dpp_f64<0x4E, 0xF>(am); am = o > am ? o : am;
+      o = dpp_f64<0x141, 0xF>(s2); s2 += o; o = dpp_f64<0x141, 0xF>(am); am = o > am ? o : am;
+      o = dpp_f64<0x140, 0xF>(s2); s2 += o; o = dpp_f64<0x140, 0xF>(am); am = o > am ? o : am;
+      o = dpp_f64<0x142, 0xA>(s2); s2 += o; o = dpp_f64<0x142, 0xA>(am); am = o > am ? o : am;
+      o = dpp_f64<0x143, 0xC>(s2); s2 += o; o = dpp_f64<0x143, 0xC>(am); am = o > am ? o : am;
     }
-    if (lane == 0) {
+    if (lane == 63) {
       cell_sumsq[c] = s2;
       cell_amax[c] = am;
       if (cell_stats) {

@@ -204,23 +204,6 @@ __device__ __forceinline__ void mp_add(const float4 r, double (&acc)[T]) {
   }
 }
 
-// One DPP move of a double (two 32-bit halves).  With every row enabled each
-// lane reads its source lane; with a partial row mask the lanes of the other
-// rows read 0.
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ double mp_dpp(double v) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  int lo, hi;
-  if constexpr (kRowMask == 0xF) {
-    lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, kCtrl, 0xF, 0xF, true);
-    hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), kCtrl, 0xF, 0xF, true);
-  } else {
-    lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, kCtrl, kRowMask, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), kCtrl, kRowMask, 0xF, false);
-  }
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
 // A lane's share of its wave: particles [beg, end) of global cell `cell`
 // (cell < 0: none), lane i of the cell's n = L lanes.
 struct MpLane {
@@ -315,27 +298,27 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
   // writes the row.  An empty cell's lane writes zeros.
   if (depth >= 1) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0xB1, 0xF>(acc[t]);   // quad_perm [1,0,3,2]
+    for (int t = 0; t < T; ++t) acc[t] += dpp_f64<0xB1, 0xF>(acc[t]);   // quad_perm [1,0,3,2]
   }
   if (depth >= 2) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x4E, 0xF>(acc[t]);   // quad_perm [2,3,0,1]
+    for (int t = 0; t < T; ++t) acc[t] += dpp_f64<0x4E, 0xF>(acc[t]);   // quad_perm [2,3,0,1]
   }
   if (depth >= 3) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x141, 0xF>(acc[t]);  // row_half_mirror
+    for (int t = 0; t < T; ++t) acc[t] += dpp_f64<0x141, 0xF>(acc[t]);  // row_half_mirror
   }
   if (depth >= 4) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x140, 0xF>(acc[t]);  // row_mirror
+    for (int t = 0; t < T; ++t) acc[t] += dpp_f64<0x140, 0xF>(acc[t]);  // row_mirror
   }
   if (depth >= 5) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x142, 0xA>(acc[t]);  // row_bcast:15 -> rows 1, 3
+    for (int t = 0; t < T; ++t) acc[t] += dpp_f64<0x142, 0xA>(acc[t]);  // row_bcast:15 -> rows 1, 3
   }
   if (depth >= 6) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] += mp_dpp<0x143, 0xC>(acc[t]);  // row_bcast:31 -> rows 2, 3
+    for (int t = 0; t < T; ++t) acc[t] += dpp_f64<0x143, 0xC>(acc[t]);  // row_bcast:31 -> rows 2, 3
   }
   if (ln.cell >= 0 && ln.i == ln.n - 1) {
     double* dst = out + (int64_t)ln.cell * TT + base;

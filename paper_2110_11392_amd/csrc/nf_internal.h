@@ -211,6 +211,23 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
                       const float* pos, const abacus_nf_binned* out, const BinWork& w,
                       hipStream_t s);
 
+// One DPP move of a double (two 32-bit halves).  With every row enabled each
+// lane reads its source lane; with a partial row mask the lanes of the other
+// rows read 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  int lo, hi;
+  if constexpr (kRowMask == 0xF) {
+    lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, kCtrl, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), kCtrl, 0xF, 0xF, true);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, kCtrl, kRowMask, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), kCtrl, kRowMask, 0xF, false);
+  }
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Wave priority from the work left in the wave's current task (sources still
 // to visit), so the SIMD's instruction arbiter favours the waves with the most
 // work left instead of the oldest waves.  With age order alone the last waves

@@ -144,7 +144,7 @@ struct Layout {
   // shared
   size_t boxtab;
   // binning region
-  size_t counts, keys0, keys1, vals0, vals1, hist, hist_scan, bin_scan;
+  size_t keys0, keys1, vals0, vals1, hist, hist_scan, bin_scan;
   // force / adjoint region (overlaps the binning region)
   size_t pencil_counts, item_base, items, item_bucket, item_slot, item_cost, tasks, ctrl, plan_scan,
       partial, mom,
@@ -165,7 +165,6 @@ Layout layout(const Resolved& r) {
   const size_t region = o;
   const int64_t n = r.n_total, c = r.cells_total;
   const int64_t rb = radix_blocks(n);
-  L.counts = take(4 * (size_t)c);
   L.keys0 = take(4 * (size_t)n);
   L.keys1 = take(4 * (size_t)n);
   L.vals0 = take(4 * (size_t)n);
@@ -356,7 +355,6 @@ int abacus_nf_bin(const abacus_nf_box* boxes, int nboxes, const float* pos,
   DevBox* dboxes = at<DevBox>(ws, L.boxtab);
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
   BinWork w;
-  w.counts = at<int32_t>(ws, L.counts);
   w.keys[0] = at<int32_t>(ws, L.keys0);
   w.keys[1] = at<int32_t>(ws, L.keys1);
   w.vals[0] = at<int32_t>(ws, L.vals0);

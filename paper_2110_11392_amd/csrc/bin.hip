@@ -1,5 +1,6 @@
-// Cell binning: FP64 cell assignment, per-cell counts, a stable LSD radix sort
-// of (cell, particle) and the gather of FP32 cell-relative offsets.
+// Cell binning: FP64 cell assignment, a stable LSD radix sort of (cell,
+// particle), the cell offsets read off the sorted keys, and the gather of FP32
+// cell-relative offsets.
 //
 // Sec. 2.2: particles live on a K^3 grid of cells, slabs along x, pencils
 // along z, so the linear cell id is (x K + y) K + z.  Sec. 3.5.1: positions are
@@ -36,12 +37,13 @@ __device__ __forceinline__ CellCoord cell_coord(float x, double cpl, int K) {
   return r;
 }
 
-// Pass 1: global cell id per particle, key/value init, per-cell counts.
+// Pass 1: global cell id per particle and key/value init.  (No per-cell
+// counting here: device-wide atomics on the counts of crowded cells cost more
+// than the whole radix sort; the offsets come from the sorted keys instead.)
 __global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ boxes, int nboxes,
                                                     int64_t n_total, const float* __restrict__ pos,
                                                     int32_t* __restrict__ keys,
                                                     int32_t* __restrict__ vals,
-                                                    int32_t* __restrict__ counts,
                                                     int32_t* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_total) return;
@@ -55,7 +57,21 @@ __global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ b
   const int cell = boxes[b].cell_base + (x.c * K + y.c) * K + z.c;
   keys[i] = cell;
   vals[i] = (int32_t)i;
-  atomicAdd(&counts[cell], 1);
+}
+
+// Cell offsets from the sorted keys: slot s starts every cell in
+// (key[s-1], key[s]] (slot 0: every cell up to key[0]); the last slot also
+// closes the cells after its key and the end entry offsets[cells] = n.
+__global__ __launch_bounds__(256) void k_cell_offsets(const int32_t* __restrict__ sorted_keys,
+                                                      int64_t n, int64_t cells,
+                                                      int32_t* __restrict__ offsets) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t cur = sorted_keys[s];
+  const int64_t prev = s > 0 ? sorted_keys[s - 1] : -1;
+  for (int64_t c = prev + 1; c <= cur; ++c) offsets[c] = (int32_t)s;
+  if (s == n - 1)
+    for (int64_t c = cur + 1; c <= cells; ++c) offsets[c] = (int32_t)n;
 }
 
 // Radix pass, step 1: per-block digit histogram, stored digit-major so that one
@@ -168,15 +184,13 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
                       const float* pos, const abacus_nf_binned* out, const BinWork& w,
                       hipStream_t s) {
   ANF_TRY(fill_i32(out->status, 0, 1, s));
-  ANF_TRY(fill_i32(w.counts, 0, cells_total, s));
-  if (n_total > 0) {
+  if (n_total == 0) return fill_i32(out->cell_offsets, 0, cells_total + 1, s);
+  {
     const unsigned g = (unsigned)((n_total + 255) / 256);
     hipLaunchKernelGGL(k_bin_assign, dim3(g), dim3(256), 0, s, boxes, nboxes, n_total, pos,
-                       w.keys[0], w.vals[0], w.counts, out->status);
+                       w.keys[0], w.vals[0], out->status);
     ANF_TRY(hipGetLastError());
   }
-  ANF_TRY(exclusive_scan(w.counts, out->cell_offsets, cells_total, w.scan_tmp, s));
-  if (n_total == 0) return hipSuccess;
 
   const int bits = key_bits(cells_total);
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
@@ -203,6 +217,10 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
     kin = kout;
     vin = vout;
   }
+  // kin holds the sorted keys (the unsorted ones when no pass ran: a single cell)
+  hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, kin,
+                     n_total, cells_total, out->cell_offsets);
+  ANF_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gather_rel, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, boxes,
                      nboxes, n_total, pos, out->perm, reinterpret_cast<float4*>(out->rel));
   return hipGetLastError();

@@ -199,7 +199,6 @@ hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t cells_tota
 
 // bin.hip
 struct BinWork {
-  int32_t* counts;   // cells_total
   int32_t* keys[2];  // n_total each
   int32_t* vals[2];  // n_total each
   int32_t* hist;     // 256 * radix blocks

@@ -175,12 +175,13 @@ __global__ __launch_bounds__(256) void k_pack_sources(const float4* __restrict__
   src3[3 * s + 2] = r.z;
 }
 
-// The production shapes (kU <= 4, no density, no pair counter) fit 8 waves per
-// SIMD once their scalar registers are capped; without the cap the compiler
-// takes about 105 SGPRs and 7 waves.  The other variants would spill, so they
+// The production shapes (kU <= 4, no pair counter) fit 8 waves per SIMD once
+// their scalar registers are capped; without the cap the compiler takes about
+// 105 SGPRs and 7 waves.  (With the density estimate at unroll 4, 12 bytes
+// spill outside the pair loop.)  The other variants would spill more, so they
 // keep the compiler's own choice.
 template <int kU, bool kCount, bool kDens>
-constexpr int fwd_min_waves() { return kU <= 4 && !kCount && !kDens ? 8 : 1; }
+constexpr int fwd_min_waves() { return kU <= 4 && !kCount ? 8 : 1; }
 
 template <int kAcc, bool kCount, int kU, bool kPipe, bool kDens>
 __global__ __launch_bounds__(256)

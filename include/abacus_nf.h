@@ -128,6 +128,8 @@ int abacus_nf_workspace_bytes(const abacus_nf_box *boxes, int nboxes, size_t *by
  *        floor(t) mod K and the offset is t - (floor(t) + 1/2) rounded once to
  *        FP32 (a coordinate on a face belongs to the higher cell).
  *   out  caller-allocated arrays (sizes in abacus_nf_binned); all are written.
+ *        With no particles at all, pos, perm and rel may be NULL (here and in
+ *        every entry point taking a binned set) and every offset is 0.
  * The status word is cleared and then set if any coordinate is non-finite or
  * |t| >= 2^30.
  */

@@ -316,8 +316,9 @@ PlanWork plan_work(void* ws, const Layout& L) {
   return w;
 }
 
-bool binned_ok(const abacus_nf_binned* b) {
-  return b && b->cell_offsets && b->perm && b->rel && b->status;
+// The per-particle arrays may be NULL when there are no particles.
+bool binned_ok(const abacus_nf_binned* b, int64_t n_total) {
+  return b && b->cell_offsets && b->status && (n_total == 0 || (b->perm && b->rel));
 }
 
 }  // namespace
@@ -348,7 +349,7 @@ int abacus_nf_bin(const abacus_nf_box* boxes, int nboxes, const float* pos,
   Resolved r;
   int rc = resolve(boxes, nboxes, &r);
   if (rc) return rc;
-  if (!binned_ok(out) || (r.n_total > 0 && !pos)) return ABACUS_NF_EINVAL;
+  if (!binned_ok(out, r.n_total) || (r.n_total > 0 && !pos)) return ABACUS_NF_EINVAL;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -377,7 +378,7 @@ int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_bin
   AccMode mode;
   if ((rc = acc_mode(flags, &mode))) return rc;
   const bool count = (flags & ABACUS_NF_COUNT_PAIRS) != 0;
-  if (!binned_ok(b) || (r.n_total > 0 && !acc) || (count && !pair_count)) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b, r.n_total) || (r.n_total > 0 && !acc) || (count && !pair_count)) return ABACUS_NF_EINVAL;
   if (density && (count || !r.density_ok)) return ABACUS_NF_EINVAL;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
@@ -415,7 +416,7 @@ int abacus_nf_forces_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   Resolved r;
   int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
-  if (!binned_ok(b) || (r.n_total > 0 && !acc)) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b, r.n_total) || (r.n_total > 0 && !acc)) return ABACUS_NF_EINVAL;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -447,7 +448,7 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   AccMode mode;
   if ((rc = acc_mode(flags, &mode))) return rc;
   if (flags & ABACUS_NF_COUNT_PAIRS) return ABACUS_NF_EINVAL;
-  if (!binned_ok(b) || (r.n_total > 0 && (!wv || !grad))) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b, r.n_total) || (r.n_total > 0 && (!wv || !grad))) return ABACUS_NF_EINVAL;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -533,7 +534,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
   AccMode mode;
   if ((rc = acc_mode(flags, &mode))) return rc;
   if (flags & ABACUS_NF_COUNT_PAIRS) return ABACUS_NF_EINVAL;
-  if (!binned_ok(b) || (r.n_total > 0 && !scratch)) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b, r.n_total) || (r.n_total > 0 && !scratch)) return ABACUS_NF_EINVAL;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -724,7 +725,7 @@ int abacus_nf_multipoles(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   if (rc) return rc;
   bool reduced = false;
   if ((rc = mp_args(order, flags, &reduced))) return rc;
-  if (!binned_ok(b) || !out) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b, r.n_total) || !out) return ABACUS_NF_EINVAL;
   const MpLayout L = mp_layout(r, order, reduced);
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0 || ws_bytes < L.total)
     return ABACUS_NF_EWORKSPACE;
@@ -766,7 +767,7 @@ int abacus_nf_kick_drift(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   Resolved r;
   int rc = resolve(boxes, nboxes, &r);
   if (rc) return rc;
-  if (!binned_ok(b) || !kick || !drift) return ABACUS_NF_EINVAL;
+  if (!binned_ok(b, r.n_total) || !kick || !drift) return ABACUS_NF_EINVAL;
   if (r.n_total > 0 && (!pos || !vel || !acc)) return ABACUS_NF_EINVAL;
   for (int i = 0; i < nboxes; ++i) {
     if (!std::isfinite(kick[i]) || !std::isfinite(drift[i])) return ABACUS_NF_EINVAL;

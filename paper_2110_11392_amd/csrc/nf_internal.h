@@ -227,6 +227,26 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// Task index for a wave of a persistent pair kernel.  The wave's first task is
+// its own index in the grid (no atomic: every wave starts at once, and 8192
+// atomics on one counter would hand out the last first task tens of
+// microseconds late); later tasks come from the shared counter, offset by the
+// grid's wave count.  `first` is wave-uniform, and every lane takes part in
+// the atomic (lane 0 adds 1, the others 0) so no divergent branch precedes
+// the caller's wave-uniform exit test.
+__device__ __forceinline__ int next_task(int32_t* head, bool& first) {
+  const int waves_per_block = (int)(blockDim.x >> 6);
+  int t;
+  if (first) {
+    t = (int)blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6);
+    first = false;
+  } else {
+    t = atomicAdd(head, (threadIdx.x & 63) == 0 ? 1 : 0);
+    t = __shfl(t, 0, 64) + (int)gridDim.x * waves_per_block;
+  }
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
 // Wave priority from the work left in the wave's current task (sources still
 // to visit), so the SIMD's instruction arbiter favours the waves with the most
 // work left instead of the oldest waves.  With age order alone the last waves

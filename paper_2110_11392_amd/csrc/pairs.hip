@@ -197,11 +197,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
   const int n_whole = uniform(ctrl[kCtrlNWhole]);
   const int n_split = uniform(ctrl[kCtrlNSplit]);
   const int slices = uniform(ctrl[kCtrlSlices]);
+  bool first = true;
   while (true) {
-    // Every lane takes part in the atomic (lane 0 adds 1, the others 0) so no
-    // divergent branch precedes the wave-uniform exit test below.
-    int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
-    t = uniform(__shfl(t, 0, 64));
+    const int t = next_task(&ctrl[kCtrlHead], first);
     if (t >= n_tasks) break;
     const int task = uniform(tasks[t]);
     const int code = task & kTaskCodeMask;  // 0: whole item; c > 0: x offset c - 1 - R only

@@ -87,9 +87,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     double* __restrict__ acc_out) {
   const int lane = threadIdx.x & 63;
   const int n_tasks = uni64(ctrl[kCtrlNTasks]);
+  bool first = true;
   while (true) {
-    int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
-    t = uni64(__shfl(t, 0, 64));
+    const int t = next_task(&ctrl[kCtrlHead], first);
     if (t >= n_tasks) break;
     const int item = uni64(tasks[t]) >> kTaskShift;
     const int4 it = items[item];

@@ -191,11 +191,9 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
   const int n_whole = uni(ctrl[kCtrlNWhole]);
   const int n_split = uni(ctrl[kCtrlNSplit]);
   const int slices = uni(ctrl[kCtrlSlices]);
+  bool first = true;
   while (true) {
-    // Every lane takes part in the atomic (lane 0 adds 1, the others 0) so no
-    // divergent branch precedes the wave-uniform exit test below.
-    int t = atomicAdd(&ctrl[kCtrlHead], lane == 0 ? 1 : 0);
-    t = uni(__shfl(t, 0, 64));
+    const int t = next_task(&ctrl[kCtrlHead], first);
     if (t >= n_tasks) break;
     const int task = uni(tasks[t]);
     const int code = task & kTaskCodeMask;  // 0: whole item; c > 0: x offset c - 1 - R only

@@ -92,6 +92,20 @@ def test_bin_bit_exact_configs(nfmod, name):
     check_bin(nfmod, synth.config(name), name)
 
 
+@pytest.mark.parametrize("label,boxes", [
+    # no particle at all: every offset is 0
+    ("all_empty", [synth.Box(np.zeros((0, 3), np.float32), 1.0, 5, 2, 1 / 500),
+                   synth.Box(np.zeros((0, 3), np.float32), 2.0, 6, 2, 1 / 500)]),
+    # one cell per box (R = 0, K = 1): the sort has no pass at all
+    ("single_cell", [synth.Box(synth.uniform(300, 21), 1.0, 1, 0, 1 / 500)]),
+    # empty cells before the first and after the last occupied cell
+    ("sparse_corner", [synth.Box((np.float32(0.95) + np.float32(0.04) *
+                                  synth.uniform(200, 22)).astype(np.float32), 1.0, 9, 2, 1 / 900)]),
+])
+def test_bin_offsets_edge_cases(nfmod, label, boxes):
+    check_bin(nfmod, boxes, label)
+
+
 def test_bin_adversarial_faces_and_wrap(nfmod):
     K = 8
     rng = np.random.default_rng(3)

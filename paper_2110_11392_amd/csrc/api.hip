@@ -628,7 +628,8 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
 // ---- cell multipoles ---------------------------------------------------------
 
 struct MpLayout {
-  size_t boxtab, keys, hist, base, cursor, waves, sorted, span, full, total;
+  size_t boxtab, keys, hist, base, cursor, waves, sorted, span, full, red_coef, red_src, red_cnt,
+      total;
 };
 
 MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
@@ -650,6 +651,9 @@ MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
   L.full = reduced ? take(sizeof(double) * (size_t)multipole_terms(order, false) *
                           (size_t)r.cells_total)
                    : 0;
+  L.red_coef = reduced ? take(sizeof(double) * 81 * 16) : 0;
+  L.red_src = reduced ? take(4 * 81 * 16) : 0;
+  L.red_cnt = reduced ? take(4 * 81) : 0;
   L.total = o;
   return L;
 }
@@ -742,6 +746,9 @@ int abacus_nf_multipoles(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   w.sorted = at<int32_t>(ws, L.sorted);
   w.span = at<int2>(ws, L.span);
   w.full = reduced ? at<double>(ws, L.full) : nullptr;
+  w.red_coef = reduced ? at<double>(ws, L.red_coef) : nullptr;
+  w.red_src = reduced ? at<int32_t>(ws, L.red_src) : nullptr;
+  w.red_cnt = reduced ? at<int32_t>(ws, L.red_cnt) : nullptr;
   Timer t(4, s);
   ANF_HIP(launch_multipoles(dboxes, nboxes, r.cells_total, order, reduced, w, b->cell_offsets,
                             b->rel, out, s),

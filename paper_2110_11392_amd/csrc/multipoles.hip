@@ -462,19 +462,16 @@ __device__ __forceinline__ double mp_fact(int n) {
   return f;
 }
 
-// Each block first tabulates, in LDS, the sources and coefficients of every
-// reduced term (at most 15 each for p <= 8), then its threads take (cell,
-// reduced term) pairs -- consecutive threads share a cell row and write
-// consecutive outputs.
+// The reduction table: for each reduced term r its sources (complete-basis
+// indices) and coefficients, at most 15 each for p <= 8.  One block writes it
+// once per call.
 constexpr int kMpRedSrc = 16;
+constexpr int kMpRedCells = 16;
 
-__global__ __launch_bounds__(256) void k_mp_reduce(const double* __restrict__ full, int p,
-                                                   int64_t cells, double* __restrict__ out) {
-  __shared__ double coef[81 * kMpRedSrc];
-  __shared__ short src[81 * kMpRedSrc];
-  __shared__ int cnt[81];
+__global__ __launch_bounds__(128) void k_mp_reduce_table(int p, double* __restrict__ coef,
+                                                         int32_t* __restrict__ src,
+                                                         int32_t* __restrict__ cnt) {
   const int RT = (p + 1) * (p + 1);
-  const int TT = mp_terms_a(p, 0, p);
   for (int r = threadIdx.x; r < RT; r += blockDim.x) {
     // decode reduced term r -> (a, b, c0), enumerated a, b, then c0 in {0, 1}
     int rr = r, a = 0, b = 0;
@@ -499,21 +496,58 @@ __global__ __launch_bounds__(256) void k_mp_reduce(const double* __restrict__ fu
                                   (mp_fact(m) / (mp_fact(i) * mp_fact(m - i))) * mp_fact(a) *
                                   mp_fact(b) * mp_fact(c0) /
                                   (mp_fact(sa) * mp_fact(sb) * mp_fact(sc));
-        src[r * kMpRedSrc + n] = (short)mp_index(p, sa, sb, sc);
+        src[r * kMpRedSrc + n] = mp_index(p, sa, sb, sc);
         ++n;
       }
     cnt[r] = n;
   }
-  __syncthreads();
-  const int64_t total = cells * RT;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cell = idx / RT;
-    const int r = (int)(idx - cell * RT);
-    const double* row = full + cell * TT;
-    double sum = 0.0;
-    for (int e = 0; e < cnt[r]; ++e) sum += coef[r * kMpRedSrc + e] * row[src[r * kMpRedSrc + e]];
-    out[idx] = sum;
+}
+
+// Each thread owns one reduced term r (its table entries in registers) and a
+// group of cells; the block walks chunks of kMpRedCells consecutive cells,
+// whose complete rows (contiguous in memory) are first copied into LDS with
+// coalesced loads.  Threads r = 0..RT-1 of a group write one cell's reduced
+// row, consecutive in memory.
+__global__ __launch_bounds__(256) void k_mp_reduce(const double* __restrict__ full, int p,
+                                                   int64_t cells,
+                                                   const double* __restrict__ tab_coef,
+                                                   const int32_t* __restrict__ tab_src,
+                                                   const int32_t* __restrict__ tab_cnt,
+                                                   double* __restrict__ out) {
+  __shared__ double rows[kMpRedCells * 165];
+  const int RT = (p + 1) * (p + 1);
+  const int TT = mp_terms_a(p, 0, p);
+  const int groups = (int)blockDim.x / RT;
+  const int t = threadIdx.x;
+  const int r = t % RT, g = t / RT;
+  const bool active = g < groups;
+  double cf[kMpRedSrc];
+  int sr[kMpRedSrc];
+  const int n = active ? tab_cnt[r] : 0;
+#pragma unroll
+  for (int e = 0; e < kMpRedSrc; ++e) {
+    cf[e] = e < n ? tab_coef[r * kMpRedSrc + e] : 0.0;
+    sr[e] = e < n ? tab_src[r * kMpRedSrc + e] : 0;
+  }
+  const int64_t chunks = (cells + kMpRedCells - 1) / kMpRedCells;
+  for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+    const int64_t c0 = ch * kMpRedCells;
+    const int nc = (int)(cells - c0 < kMpRedCells ? cells - c0 : kMpRedCells);
+    __syncthreads();  // the previous chunk's rows are consumed
+    const double* in = full + c0 * TT;
+    for (int k = t; k < nc * TT; k += blockDim.x) rows[k] = in[k];
+    __syncthreads();
+    if (active) {
+      double* dst = out + c0 * RT;
+      for (int cl = g; cl < nc; cl += groups) {
+        const double* row = rows + cl * TT;
+        double sum = 0.0;
+#pragma unroll
+        for (int e = 0; e < kMpRedSrc; ++e)
+          if (e < n) sum += cf[e] * row[sr[e]];
+        dst[cl * RT + r] = sum;
+      }
+    }
   }
 }
 
@@ -559,11 +593,13 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
     default: e = launch_mp_t<8>(boxes, nboxes, w, off, rel, full, s); break;
   }
   if (e != hipSuccess || !reduced) return e;
-  const int64_t threads = cells_total * (int64_t)(order + 1) * (order + 1);
-  int64_t blocks = (threads + 255) / 256;
+  hipLaunchKernelGGL(k_mp_reduce_table, dim3(1), dim3(128), 0, s, order, w.red_coef, w.red_src,
+                     w.red_cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int64_t blocks = (cells_total + kMpRedCells - 1) / kMpRedCells;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_mp_reduce, dim3((unsigned)blocks), dim3(256), 0, s, w.full, order,
-                     cells_total, out);
+                     cells_total, w.red_coef, w.red_src, w.red_cnt, out);
   return hipGetLastError();
 }
 

@@ -178,6 +178,9 @@ struct MpWork {
   int32_t* sorted;        // cells: cell ids sorted by bucket
   int2* span;             // cells: (first particle, count) of each sorted cell
   double* full;           // cells_total x complete terms (only for the reduced basis)
+  double* red_coef;       // 81 x 16 reduction coefficients (reduced basis only)
+  int32_t* red_src;       // 81 x 16 complete-basis sources of each reduced term
+  int32_t* red_cnt;       // 81 sources per reduced term
 };
 int64_t multipole_terms(int p, bool reduced);
 hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_total, int order,

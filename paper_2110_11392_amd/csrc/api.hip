@@ -61,7 +61,7 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = f
     if (x.radius < 0 || x.cpd < 2 * (int64_t)x.radius + 1) return ABACUS_NF_EINVAL;
     if (!(x.eps_plummer > 0.0) || !std::isfinite(x.eps_plummer)) return ABACUS_NF_EINVAL;
     const int64_t K = x.cpd;
-    if (K > 2000) return ABACUS_NF_ERANGE;
+    if (K > kMaxCellsPerDim) return ABACUS_NF_ERANGE;
     const int64_t cells = K * K * K;
     const double cpl = (double)K / x.box;
     const double eps_s = kSplineOverPlummer * x.eps_plummer;

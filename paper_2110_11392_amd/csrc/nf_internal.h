@@ -18,6 +18,8 @@ constexpr int kTile = 64;
 constexpr int kChunk = 64;
 // Most cells one work item's 64 sinks may span along its pencil (the planner's
 // span parameter is 1..kMaxSpan; kDefaultSpan unless the autotuner chose another).
+// Largest cells per dimension of a box (larger K is rejected with ERANGE).
+constexpr int kMaxCellsPerDim = 2000;
 constexpr int kMaxSpan = 3;
 constexpr int kDefaultSpan = 2;
 // Cost buckets for the longest-first work queue, descending: four per octave

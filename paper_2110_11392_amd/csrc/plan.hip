@@ -18,21 +18,23 @@
 namespace anf {
 
 // item = {box | count << 16, cx | cy << 16, za | zb << 16, first sink}.
+// The walk reads the pencil's K + 1 cell offsets from `po` (LDS): po[z] is the
+// first sorted slot of cell z of the pencil, po[K] one past its last.
 template <bool kEmit>
-__device__ int walk_pencil(const int32_t* __restrict__ off, int cell0, int K, int b, int cx, int cy,
-                           int span, int4* __restrict__ out) {
+__device__ int walk_pencil(const int32_t* po, int K, int b, int cx, int cy, int span,
+                           int4* __restrict__ out) {
   int nitems = 0;
-  int i = off[cell0];
-  const int end = off[cell0 + K];
+  int i = po[0];
+  const int end = po[K];
   int z = 0;
   while (i < end) {
-    while (off[cell0 + z + 1] <= i) ++z;  // cell of sink i (skips empty cells)
+    while (po[z + 1] <= i) ++z;  // cell of sink i (skips empty cells)
     const int za = z;
-    const int span_end = off[cell0 + (za + span < K ? za + span : K)];
+    const int span_end = po[za + span < K ? za + span : K];
     int stop = i + kTile;
     stop = stop < span_end ? stop : span_end;
     int zb = za;
-    while (off[cell0 + zb + 1] < stop) ++zb;  // cell of sink stop-1
+    while (po[zb + 1] < stop) ++zb;  // cell of sink stop-1
     if (kEmit) out[nitems] = make_int4(b | ((stop - i) << 16), cx | (cy << 16), za | (zb << 16), i);
     ++nitems;
     i = stop;
@@ -40,31 +42,40 @@ __device__ int walk_pencil(const int32_t* __restrict__ off, int cell0, int K, in
   return nitems;
 }
 
-__global__ __launch_bounds__(64) void k_plan_count(const DevBox* __restrict__ boxes, int nboxes,
-                                                   int64_t pencils, const int32_t* __restrict__ off,
-                                                   int span, int32_t* __restrict__ counts) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pencils) return;
+// One wave per pencil: the lanes copy the pencil's offsets into LDS with
+// coalesced loads, then lane 0 walks it (a chain of LDS reads instead of a
+// chain of dependent global loads).
+template <bool kEmit>
+__device__ void plan_pencil(const DevBox* __restrict__ boxes, int nboxes, int64_t p,
+                            const int32_t* __restrict__ off, int span, int32_t* __restrict__ counts,
+                            const int32_t* __restrict__ base, int4* __restrict__ items) {
+  __shared__ int32_t po[kMaxCellsPerDim + 1];
   const int b = nboxes == 1 ? 0 : find_box_by_pencil(boxes, nboxes, (int)p);
   const int K = boxes[b].K;
   const int local = (int)p - boxes[b].pencil_base;
   const int cx = local / K, cy = local - (local / K) * K;
   const int cell0 = boxes[b].cell_base + local * K;
-  counts[p] = walk_pencil<false>(off, cell0, K, b, cx, cy, span, nullptr);
+  for (int z = threadIdx.x; z <= K; z += blockDim.x) po[z] = off[cell0 + z];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (kEmit)
+      walk_pencil<true>(po, K, b, cx, cy, span, items + base[p]);
+    else
+      counts[p] = walk_pencil<false>(po, K, b, cx, cy, span, nullptr);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_plan_count(const DevBox* __restrict__ boxes, int nboxes,
+                                                   int64_t pencils, const int32_t* __restrict__ off,
+                                                   int span, int32_t* __restrict__ counts) {
+  plan_pencil<false>(boxes, nboxes, blockIdx.x, off, span, counts, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(64) void k_plan_emit(const DevBox* __restrict__ boxes, int nboxes,
                                                   int64_t pencils, const int32_t* __restrict__ off,
                                                   int span, const int32_t* __restrict__ base,
                                                   int4* __restrict__ items) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= pencils) return;
-  const int b = nboxes == 1 ? 0 : find_box_by_pencil(boxes, nboxes, (int)p);
-  const int K = boxes[b].K;
-  const int local = (int)p - boxes[b].pencil_base;
-  const int cx = local / K, cy = local - (local / K) * K;
-  const int cell0 = boxes[b].cell_base + local * K;
-  walk_pencil<true>(off, cell0, K, b, cx, cy, span, items + base[p]);
+  plan_pencil<true>(boxes, nboxes, blockIdx.x, off, span, nullptr, base, items);
 }
 
 // Sources in cells z = lo..hi (unwrapped, periodic) of one column.
@@ -242,7 +253,7 @@ int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_tot
 hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils, const int32_t* off,
                        int span, int slices, const PlanWork& w, hipStream_t s) {
   span = span < 1 ? 1 : (span > kMaxSpan ? kMaxSpan : span);
-  const unsigned gp = (unsigned)((pencils + 63) / 64);
+  const unsigned gp = (unsigned)pencils;  // one wave per pencil
   hipLaunchKernelGGL(k_plan_count, dim3(gp), dim3(64), 0, s, boxes, nboxes, pencils, off, span,
                      w.pencil_counts);
   ANF_TRY(hipGetLastError());

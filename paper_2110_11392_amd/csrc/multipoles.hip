@@ -471,6 +471,9 @@ constexpr int kMpRedCells = 16;
 __global__ __launch_bounds__(128) void k_mp_reduce_table(int p, double* __restrict__ coef,
                                                          int32_t* __restrict__ src,
                                                          int32_t* __restrict__ cnt) {
+  __shared__ double fact[2 * kMaxMultipoleOrder + 1];  // n! for n <= 2p (exact in FP64)
+  if ((int)threadIdx.x <= 2 * kMaxMultipoleOrder) fact[threadIdx.x] = mp_fact((int)threadIdx.x);
+  __syncthreads();
   const int RT = (p + 1) * (p + 1);
   for (int r = threadIdx.x; r < RT; r += blockDim.x) {
     // decode reduced term r -> (a, b, c0), enumerated a, b, then c0 in {0, 1}
@@ -493,9 +496,8 @@ __global__ __launch_bounds__(128) void k_mp_reduce_table(int p, double* __restri
         const int sa = a - 2 * i, sb = b - 2 * (m - i), sc = c0 + 2 * m;
         if (sa < 0 || sb < 0) continue;
         coef[r * kMpRedSrc + n] = ((m & 1) ? -1.0 : 1.0) *
-                                  (mp_fact(m) / (mp_fact(i) * mp_fact(m - i))) * mp_fact(a) *
-                                  mp_fact(b) * mp_fact(c0) /
-                                  (mp_fact(sa) * mp_fact(sb) * mp_fact(sc));
+                                  (fact[m] / (fact[i] * fact[m - i])) * fact[a] * fact[b] *
+                                  fact[c0] / (fact[sa] * fact[sb] * fact[sc]);
         src[r * kMpRedSrc + n] = mp_index(p, sa, sb, sc);
         ++n;
       }

@@ -10,20 +10,22 @@
 // How it maps to CDNA4:
 //   * each cell gets L lanes (a power of two, about n/16 of them, at most 64)
 //     and each lane sums `per` = ceil(n/L) consecutive particles of the cell;
-//   * a wave first copies its cells' offsets into LDS with coalesced loads (64
-//     consecutive particles per instruction), so the per-lane reads of the
-//     passes hit LDS instead of scattered global lines (cells needing more than
-//     16 particles per lane read global memory directly);
 //   * cells are bucketed by (L, per) with a counting sort, and a work wave
 //     takes 64/L cells of one bucket, so all 64 lanes of a wave do the same
 //     number of particles -- the balance the paper gets from its "step-down"
 //     remainder iterations;
-//   * a lane keeps its partial moments in FP64 VGPRs (passes of at most 64
+//   * a wave stages its cells' offsets in LDS with straight-line coalesced
+//     loads, all in flight together, in particle-row order (particle m of a
+//     lane's segment at slot 64 m + lane), and requests the next work wave's
+//     cell table before its own arithmetic; cells needing more than 16
+//     particles per lane read global memory directly;
+//   * a lane keeps its partial moments in FP64 VGPRs (passes of at most 56
 //     terms, split by the power of x), then each cell's L lanes are added in
-//     registers with a butterfly of lane shuffles -- a fixed pairwise order,
-//     so results are run-to-run deterministic whatever wave a cell lands in;
-//   * the first lane of each cell scales the sums by w^(a+b+c) and writes them.
-// The reduced basis is a second, HBM-bound pass over the complete rows.
+//     registers with DPP moves in a fixed pattern, so results are run-to-run
+//     deterministic whatever wave a cell lands in;
+//   * the last lane of each cell's block scales the sums by w^(a+b+c) and
+//     writes them.
+// The reduced basis is a second pass over the complete rows, staged in LDS.
 #include "nf_internal.h"
 
 namespace anf {

@@ -17,8 +17,10 @@
 //   * the periodic wrap never reaches the arithmetic: a source cell's integer
 //     offset o from the sink's cell is folded into the sink (q = p - o) once per
 //     source cell, and d = s - q uses only FP32 cell-relative coordinates;
-//   * sums are per-lane registers; a persistent grid pops items from a
-//     longest-first queue with one atomic per item.
+//   * sums are per-lane registers; a persistent grid takes items from a
+//     longest-first queue (each wave's first item by its grid index, the rest
+//     with one atomic each), and each wave's priority follows the sources left
+//     in its current item.
 #include "nf_internal.h"
 
 namespace anf {

@@ -39,7 +39,7 @@ __device__ __forceinline__ CellCoord cell_coord(float x, double cpl, int K) {
 
 // Pass 1: global cell id per particle and key/value init.  (No per-cell
 // counting here: device-wide atomics on the counts of crowded cells cost more
-// than the whole radix sort; the offsets come from the sorted keys instead.)
+// than the whole radix sort; the offsets are found in the sorted keys instead.)
 __global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ boxes, int nboxes,
                                                     int64_t n_total, const float* __restrict__ pos,
                                                     int32_t* __restrict__ keys,
@@ -59,19 +59,22 @@ __global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ b
   vals[i] = (int32_t)i;
 }
 
-// Cell offsets from the sorted keys: slot s starts every cell in
-// (key[s-1], key[s]] (slot 0: every cell up to key[0]); the last slot also
-// closes the cells after its key and the end entry offsets[cells] = n.
+// Cell offsets from the sorted keys: offsets[c] is the first slot whose key is
+// at least c (a lower bound found by binary search), so offsets[cells] = n and
+// an empty cell gets the start of the next occupied one.  One thread per cell:
+// the work is balanced however the particles are spread (a scan over slots
+// would hand a long run of empty cells to a single thread).
 __global__ __launch_bounds__(256) void k_cell_offsets(const int32_t* __restrict__ sorted_keys,
                                                       int64_t n, int64_t cells,
                                                       int32_t* __restrict__ offsets) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int64_t cur = sorted_keys[s];
-  const int64_t prev = s > 0 ? sorted_keys[s - 1] : -1;
-  for (int64_t c = prev + 1; c <= cur; ++c) offsets[c] = (int32_t)s;
-  if (s == n - 1)
-    for (int64_t c = cur + 1; c <= cells; ++c) offsets[c] = (int32_t)n;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > cells) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (sorted_keys[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  offsets[c] = (int32_t)lo;
 }
 
 // Radix pass, step 1: per-block digit histogram, stored digit-major so that one
@@ -218,8 +221,8 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
     vin = vout;
   }
   // kin holds the sorted keys (the unsorted ones when no pass ran: a single cell)
-  hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, kin,
-                     n_total, cells_total, out->cell_offsets);
+  hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((cells_total + 1 + 255) / 256)), dim3(256), 0,
+                     s, kin, n_total, cells_total, out->cell_offsets);
   ANF_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gather_rel, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, boxes,
                      nboxes, n_total, pos, out->perm, reinterpret_cast<float4*>(out->rel));

@@ -98,17 +98,26 @@ __host__ __device__ constexpr int mp_key_lanes_log2(int key) {
 
 // ---- planning: counting sort of the cells by bucket --------------------------
 
+// A planning block covers 256 ppt cells (ppt per thread, 1..16, chosen so that
+// there are about 256 blocks): the device-wide atomics on the bucket counters
+// (one per block and non-empty bucket) stay few while every CU still gets work.
+constexpr int kMpPlanPerThread = 16;
+
 __global__ __launch_bounds__(256) void k_mp_classify(const int32_t* __restrict__ off,
-                                                     int64_t cells, int32_t* __restrict__ key_out,
+                                                     int64_t cells, int ppt,
+                                                     int32_t* __restrict__ key_out,
                                                      int32_t* __restrict__ hist) {
   __shared__ int local[kMpEmpty + 1];
   for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x) local[k] = 0;
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < cells) {
-    const int key = mp_key(off[c + 1] - off[c]);
-    key_out[c] = key;
-    atomicAdd(&local[key], 1);
+#pragma unroll
+  for (int j = 0; j < kMpPlanPerThread; ++j) {
+    const int64_t c = ((int64_t)blockIdx.x * ppt + j) * 256 + threadIdx.x;
+    if (j < ppt && c < cells) {
+      const int key = mp_key(off[c + 1] - off[c]);
+      key_out[c] = key;
+      atomicAdd(&local[key], 1);
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x)
@@ -149,26 +158,36 @@ __global__ __launch_bounds__(256) void k_mp_buckets(const int32_t* __restrict__ 
 // matter: every cell's sums are independent of its position).
 __global__ __launch_bounds__(256) void k_mp_scatter(const int32_t* __restrict__ key_in,
                                                     const int32_t* __restrict__ off,
-                                                    int64_t cells, int32_t* __restrict__ cursor,
+                                                    int64_t cells, int ppt,
+                                                    int32_t* __restrict__ cursor,
                                                     int32_t* __restrict__ sorted,
                                                     int2* __restrict__ span) {
   __shared__ int cnt[kMpEmpty + 1], start[kMpEmpty + 1];
   for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x) cnt[k] = 0;
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int key = -1, rank = 0;
-  if (c < cells) {
-    key = key_in[c];
-    rank = atomicAdd(&cnt[key], 1);
+  int key[kMpPlanPerThread], rank[kMpPlanPerThread];
+#pragma unroll
+  for (int j = 0; j < kMpPlanPerThread; ++j) {
+    const int64_t c = ((int64_t)blockIdx.x * ppt + j) * 256 + threadIdx.x;
+    key[j] = -1;
+    rank[j] = 0;
+    if (j < ppt && c < cells) {
+      key[j] = key_in[c];
+      rank[j] = atomicAdd(&cnt[key[j]], 1);
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k <= kMpEmpty; k += blockDim.x)
     start[k] = cnt[k] ? atomicAdd(&cursor[k], cnt[k]) : 0;
   __syncthreads();
-  if (key >= 0) {
-    const int at = start[key] + rank;
-    sorted[at] = (int32_t)c;
-    span[at] = make_int2(off[c], off[c + 1] - off[c]);
+#pragma unroll
+  for (int j = 0; j < kMpPlanPerThread; ++j) {
+    if (key[j] >= 0) {
+      const int64_t c = ((int64_t)blockIdx.x * ppt + j) * 256 + threadIdx.x;
+      const int at = start[key[j]] + rank[j];
+      sorted[at] = (int32_t)c;
+      span[at] = make_int2(off[c], off[c + 1] - off[c]);
+    }
   }
 }
 
@@ -575,14 +594,17 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
   if (cells_total <= 0) return hipSuccess;
   hipError_t e = fill_i32(w.hist, 0, kMpBuckets, s);
   if (e != hipSuccess) return e;
-  const unsigned cg = (unsigned)((cells_total + 255) / 256);
-  hipLaunchKernelGGL(k_mp_classify, dim3(cg), dim3(256), 0, s, off, cells_total, w.keys, w.hist);
+  int64_t ppt = cells_total / (256 * 256);
+  ppt = ppt < 1 ? 1 : (ppt > kMpPlanPerThread ? kMpPlanPerThread : ppt);
+  const unsigned cg = (unsigned)((cells_total + 256 * ppt - 1) / (256 * ppt));
+  hipLaunchKernelGGL(k_mp_classify, dim3(cg), dim3(256), 0, s, off, cells_total, (int)ppt, w.keys,
+                     w.hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_mp_buckets, dim3(1), dim3(256), 0, s, w.hist, w.bucket_base, w.cursor,
                      w.bucket_waves);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mp_scatter, dim3(cg), dim3(256), 0, s, w.keys, off, cells_total, w.cursor,
-                     w.sorted, w.span);
+  hipLaunchKernelGGL(k_mp_scatter, dim3(cg), dim3(256), 0, s, w.keys, off, cells_total, (int)ppt,
+                     w.cursor, w.sorted, w.span);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   double* full = reduced ? w.full : out;
   switch (order) {

@@ -277,18 +277,26 @@ __device__ __forceinline__ void mp_pass(const float4* __restrict__ rel, const Mp
     const float* sy = sh.y + ln.lds;
     const float* sz = sh.z + ln.lds;
     if (cnt > 0) {
-      // particle m of this lane's segment sits in row m: sx[64 m]
-      float nx = sx[0], ny = sy[0], nz = sz[0];
-      for (int m = 0; m < cnt; ++m) {
-        const float4 cur = make_float4(nx, ny, nz, 0.f);
-        const int k = m + 1 < cnt ? m + 1 : m;
-        nx = sx[64 * k];
-        ny = sy[64 * k];
-        nz = sz[64 * k];
+      // Particle m of this lane's segment sits in row m: sx[64 m].  Two
+      // register sets alternate (no copies, so a wait covers only the older
+      // loads: LDS reads complete in order); the index is clamped to the
+      // segment, and a load past its end is never used.
+      float ax = sx[0], ay = sy[0], az = sz[0];
+      int m = 0;
+      for (; m + 1 < cnt; m += 2) {
+        const float bx = sx[64 * (m + 1)], by = sy[64 * (m + 1)], bz = sz[64 * (m + 1)];
         __builtin_amdgcn_sched_barrier(0);
-        mp_add<P, A0, A1>(cur, acc);
+        mp_add<P, A0, A1>(make_float4(ax, ay, az, 0.f), acc);
+        __builtin_amdgcn_sched_barrier(0);
+        const int k = m + 2 < cnt ? m + 2 : m + 1;
+        ax = sx[64 * k];
+        ay = sy[64 * k];
+        az = sz[64 * k];
+        __builtin_amdgcn_sched_barrier(0);
+        mp_add<P, A0, A1>(make_float4(bx, by, bz, 0.f), acc);
         __builtin_amdgcn_sched_barrier(0);
       }
+      if (m < cnt) mp_add<P, A0, A1>(make_float4(ax, ay, az, 0.f), acc);
     }
   } else {
   int j = beg;

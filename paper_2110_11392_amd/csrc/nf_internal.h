@@ -232,23 +232,25 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// Task index for a wave of a persistent pair kernel.  The wave's first task is
-// its own index in the grid (no atomic: every wave starts at once, and 8192
-// atomics on one counter would hand out the last first task tens of
-// microseconds late); later tasks come from the shared counter, offset by the
-// grid's wave count.  `first` is wave-uniform, and every lane takes part in
-// the atomic (lane 0 adds 1, the others 0) so no divergent branch precedes
-// the caller's wave-uniform exit test.
-__device__ __forceinline__ int next_task(int32_t* head, bool& first) {
-  const int waves_per_block = (int)(blockDim.x >> 6);
+// Task index for a wave of a persistent pair kernel.  The first n_static waves
+// of the grid (those that are resident from the start) take their own grid
+// index as their first task -- no atomic: every resident wave starts at once,
+// and 8192 atomics on one counter would hand out the last first task tens of
+// microseconds late.  Every other task comes from the shared counter, offset
+// by n_static; a grid larger than the resident set (the autotuner's grid
+// multiplier) thus leaves no task waiting for a late wave.  `first` is
+// wave-uniform, and every lane takes part in the atomic (lane 0 adds 1, the
+// others 0) so no divergent branch precedes the caller's wave-uniform exit test.
+__device__ __forceinline__ int next_task(int32_t* head, bool& first, int n_static) {
+  const int wave = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
   int t;
-  if (first) {
-    t = (int)blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6);
-    first = false;
+  if (first && wave < n_static) {
+    t = wave;
   } else {
     t = atomicAdd(head, (threadIdx.x & 63) == 0 ? 1 : 0);
-    t = __shfl(t, 0, 64) + (int)gridDim.x * waves_per_block;
+    t = __shfl(t, 0, 64) + n_static;
   }
+  first = false;
   return __builtin_amdgcn_readfirstlane(t);
 }
 

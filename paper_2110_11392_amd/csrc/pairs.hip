@@ -193,7 +193,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
     const int32_t* __restrict__ off, const float4* __restrict__ rel,
     const float* __restrict__ src3, const int32_t* __restrict__ perm, float* __restrict__ acc_out,
     float* __restrict__ dens_out, float* __restrict__ partial,
-    unsigned long long* __restrict__ pair_count) {
+    unsigned long long* __restrict__ pair_count, int n_static) {
   const int lane = threadIdx.x & 63;
   const int n_tasks = uniform(ctrl[kCtrlNTasks]);
   const int n_whole = uniform(ctrl[kCtrlNWhole]);
@@ -201,7 +201,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
   const int slices = uniform(ctrl[kCtrlSlices]);
   bool first = true;
   while (true) {
-    const int t = next_task(&ctrl[kCtrlHead], first);
+    const int t = next_task(&ctrl[kCtrlHead], first, n_static);
     if (t >= n_tasks) break;
     const int task = uniform(tasks[t]);
     const int code = task & kTaskCodeMask;  // 0: whole item; c > 0: x offset c - 1 - R only
@@ -345,11 +345,12 @@ static hipError_t launch_forward_t(const DevBox* boxes, const PlanWork& w, const
                                    float* acc, float* dens, int64_t* pair_count, int grid_mult,
                                    hipStream_t s) {
   const void* fn = reinterpret_cast<const void*>(&k_pair_forward<kAcc, kCount, kU, kPipe, kDens>);
-  const int blocks = persistent_blocks(fn, 256) * grid_mult;
+  const int resident = persistent_blocks(fn, 256);
+  const int blocks = resident * grid_mult;
   hipLaunchKernelGGL((k_pair_forward<kAcc, kCount, kU, kPipe, kDens>), dim3(blocks), dim3(256), 0,
                      s, boxes, w.items, w.tasks, w.item_cost, w.ctrl, off, reinterpret_cast<const float4*>(rel),
                      src3, perm, acc, dens, w.partial,
-                     reinterpret_cast<unsigned long long*>(pair_count));
+                     reinterpret_cast<unsigned long long*>(pair_count), resident * 4);
   return hipGetLastError();
 }
 

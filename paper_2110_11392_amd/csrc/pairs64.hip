@@ -84,12 +84,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     int32_t* __restrict__ ctrl,
     const int32_t* __restrict__ off, const float4* __restrict__ rel,
     const float* __restrict__ src3, const int32_t* __restrict__ perm,
-    double* __restrict__ acc_out) {
+    double* __restrict__ acc_out, int n_static) {
   const int lane = threadIdx.x & 63;
   const int n_tasks = uni64(ctrl[kCtrlNTasks]);
   bool first = true;
   while (true) {
-    const int t = next_task(&ctrl[kCtrlHead], first);
+    const int t = next_task(&ctrl[kCtrlHead], first, n_static);
     if (t >= n_tasks) break;
     const int item = uni64(tasks[t]) >> kTaskShift;
     const int4 it = items[item];
@@ -179,7 +179,8 @@ hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int3
   const void* fn = reinterpret_cast<const void*>(&k_pair_forward_f64);
   const int blocks = persistent_blocks(fn, 256);
   hipLaunchKernelGGL(k_pair_forward_f64, dim3(blocks), dim3(256), 0, s, boxes, w.items, w.tasks,
-                     w.item_cost, w.ctrl, off, reinterpret_cast<const float4*>(rel), src3, perm, acc);
+                     w.item_cost, w.ctrl, off, reinterpret_cast<const float4*>(rel), src3, perm, acc,
+                     blocks * 4);
   return hipGetLastError();
 }
 

@@ -185,7 +185,8 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     const DevBox* __restrict__ boxes, const int4* __restrict__ items,
     const int32_t* __restrict__ tasks, const int32_t* __restrict__ item_cost,
     int32_t* __restrict__ ctrl, const int32_t* __restrict__ off, const float* __restrict__ src6,
-    const int32_t* __restrict__ perm, float* __restrict__ grad, float* __restrict__ partial) {
+    const int32_t* __restrict__ perm, float* __restrict__ grad, float* __restrict__ partial,
+    int n_static) {
   const int lane = threadIdx.x & 63;
   const int n_tasks = uni(ctrl[kCtrlNTasks]);
   const int n_whole = uni(ctrl[kCtrlNWhole]);
@@ -193,7 +194,7 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
   const int slices = uni(ctrl[kCtrlSlices]);
   bool first = true;
   while (true) {
-    const int t = next_task(&ctrl[kCtrlHead], first);
+    const int t = next_task(&ctrl[kCtrlHead], first, n_static);
     if (t >= n_tasks) break;
     const int task = uni(tasks[t]);
     const int code = task & kTaskCodeMask;  // 0: whole item; c > 0: x offset c - 1 - R only
@@ -321,9 +322,10 @@ static hipError_t launch_vjp_t(const DevBox* boxes, const PlanWork& w, const int
                                const float* src, const int32_t* perm, float* grad, int grid_mult,
                                hipStream_t s) {
   const void* fn = reinterpret_cast<const void*>(&k_pair_vjp<kAcc, kU, kPipe>);
-  const int blocks = persistent_blocks(fn, 256) * grid_mult;
+  const int resident = persistent_blocks(fn, 256);
+  const int blocks = resident * grid_mult;
   hipLaunchKernelGGL((k_pair_vjp<kAcc, kU, kPipe>), dim3(blocks), dim3(256), 0, s, boxes, w.items,
-                     w.tasks, w.item_cost, w.ctrl, off, src, perm, grad, w.partial);
+                     w.tasks, w.item_cost, w.ctrl, off, src, perm, grad, w.partial, resident * 4);
   return hipGetLastError();
 }
 

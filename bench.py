@@ -413,7 +413,10 @@ def main():
                      "traffic": tbytes,
                      "algorithmic_flop_per_launch": (FLOP_ADJ if dominant == "adjoint"
                                                      else FLOP_FWD) * pairs,
-                     "forward_tflops": fwd_tflops, "adjoint_tflops": adj_tflops},
+                     "forward_tflops": fwd_tflops, "adjoint_tflops": adj_tflops,
+                     # the library is built without packed FP32, so one VALU
+                     # instruction per lane and cycle gives half the peak
+                     "frac_of_non_packed_fp32": achieved / (PEAK_FP32_TFLOPS / 2)},
     }
     if not args.no_rows:
         log("[bench] widened rows: density, Plummer, multipoles, kick-drift")

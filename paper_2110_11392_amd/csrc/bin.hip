@@ -97,18 +97,39 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const int32_t* __r
   hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
-// Radix pass, step 2: stable scatter.  The block walks its keys in index order,
-// 256 at a time; inside a wave the rank of a key among equal digits comes from
-// eight ballots, across waves from per-wave digit counts in LDS.
+// Radix pass, step 2: stable scatter.  The block first ranks its tile in LDS:
+// walking its keys in index order, 256 at a time, the rank of a key among equal
+// digits comes from eight ballots inside a wave and from per-wave digit counts
+// across waves; each key lands at its digit's local start (an exclusive scan of
+// the block's digit histogram) plus that rank.  The tile, now grouped by digit
+// and stable inside each digit, is then written out so that consecutive
+// threads write consecutive slots of a digit's run (coalesced, instead of one
+// scattered word per key).
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int64_t n, int shift,
-    const int32_t* __restrict__ hist_scan, int nblocks, int32_t* __restrict__ keys_out,
-    int32_t* __restrict__ vals_out) {
+    const int32_t* __restrict__ hist, const int32_t* __restrict__ hist_scan, int nblocks,
+    int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
   constexpr int kWaves = kRadixThreads / 64;
-  __shared__ int base[256];
+  static_assert(kRadixThreads == 256, "one thread per digit");
+  __shared__ int base[256], lstart[256], gbase[256];
   __shared__ int wcount[kWaves][256];
+  __shared__ int32_t skey[kRadixTile], sval[kRadixTile];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  base[t] = hist_scan[(int64_t)t * nblocks + blockIdx.x];
+  // local digit starts: exclusive scan of this block's digit counts
+  const int cnt = hist[(int64_t)t * nblocks + blockIdx.x];
+  lstart[t] = cnt;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int a = t >= d ? lstart[t - d] : 0;
+    __syncthreads();
+    lstart[t] += a;
+    __syncthreads();
+  }
+  const int excl = lstart[t] - cnt;
+  __syncthreads();
+  lstart[t] = excl;
+  base[t] = excl;
+  gbase[t] = hist_scan[(int64_t)t * nblocks + blockIdx.x];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t block0 = (int64_t)blockIdx.x * kRadixTile;
   for (int k = 0; k < kRadixItems; ++k) {
@@ -135,8 +156,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     if (valid) {
       int pos = base[d] + rank;
       for (int w = 0; w < wv; ++w) pos += wcount[w][d];
-      keys_out[pos] = key;
-      vals_out[pos] = val;
+      skey[pos] = key;
+      sval[pos] = val;
     }
     __syncthreads();
     int add = 0;
@@ -144,6 +165,16 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     base[t] += add;
     // base[] and wcount[] are read again only after the barrier at the top
     // of the next round.
+  }
+  __syncthreads();
+  const int64_t left = n - block0;
+  const int ntile = left < kRadixTile ? (int)left : kRadixTile;
+  for (int j = t; j < ntile; j += kRadixThreads) {
+    const int key = skey[j];
+    const int d = (key >> shift) & 255;
+    const int g = gbase[d] + (j - lstart[d]);
+    keys_out[g] = key;
+    vals_out[g] = sval[j];
   }
 }
 
@@ -215,7 +246,7 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
     ANF_TRY(hipGetLastError());
     ANF_TRY(exclusive_scan(w.hist, w.hist_scan, (int64_t)256 * nb, w.scan_tmp, s));
     hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kRadixThreads), 0, s, kin, vin, n_total,
-                       shift, w.hist_scan, nb, kout, vout);
+                       shift, w.hist, w.hist_scan, nb, kout, vout);
     ANF_TRY(hipGetLastError());
     kin = kout;
     vin = vout;

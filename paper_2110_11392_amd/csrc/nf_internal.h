@@ -44,7 +44,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 // Momentum reduction: chunks per box.
-constexpr int kMomChunks = 64;
+constexpr int kMomChunks = 1024;  // a multiple of 64 (the final pass: one wave per box)
 // r^2 guard: added to every squared separation so that coincident particles
 // (r = 0, including a particle with itself) give a finite f and zero force.
 constexpr float kTinyR2 = 1e-24f;

@@ -4,8 +4,9 @@
 // equal and opposite, so sum_i a_i vanishes in exact arithmetic; with FP32
 // forces it measures the accumulated rounding.  Per box this returns
 // (sum a_x, sum a_y, sum a_z, sum |a|) reduced in FP64 in a fixed order (wave
-// shuffles, then LDS, then a second fixed-order pass), so the result does not
-// depend on scheduling.
+// shuffles, then LDS, then a second fixed-order pass over kMomChunks partials
+// per box, enough blocks to fill the chip), so the result does not depend on
+// scheduling.
 #include "nf_internal.h"
 
 namespace anf {
@@ -52,9 +53,13 @@ __global__ __launch_bounds__(256) void k_momentum_partial(const DevBox* __restri
 
 __global__ __launch_bounds__(64) void k_momentum_final(const double* __restrict__ partials,
                                                        double* __restrict__ momentum) {
+  static_assert(kMomChunks % 64 == 0, "chunks per lane");
+  constexpr int kPerLane = kMomChunks / 64;
   const int b = blockIdx.x, lane = threadIdx.x;
   for (int c = 0; c < 4; ++c) {
-    double v = partials[((int64_t)b * kMomChunks + lane) * 4 + c];
+    double v = 0.0;
+    for (int q = 0; q < kPerLane; ++q)
+      v += partials[((int64_t)b * kMomChunks + lane * kPerLane + q) * 4 + c];
     v = wave_sum(v);
     if (lane == 0) momentum[4 * b + c] = v;
   }

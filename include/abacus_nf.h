@@ -198,7 +198,7 @@ const char *abacus_nf_strerror(int code);
 /* Launch shape of one pair kernel.  Every shape computes the same sums in the
  * same order per sink: the choice changes speed, never results. */
 typedef struct {
-    int32_t unroll;     /* sources per inner-loop step: 2, 4 or 8 (adjoint: 2 or 4) */
+    int32_t unroll;     /* sources per inner-loop step: 2, 4 or 8 (adjoint: 2, 3 or 4) */
     int32_t pipeline;   /* 1: request the next step's sources before using the current ones */
     int32_t span;       /* most cells one 64-sink work item spans along its pencil: 1, 2 or 3 */
     int32_t grid_mult;  /* persistent workgroups per resident slot: 1 or 2 */

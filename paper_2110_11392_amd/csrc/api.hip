@@ -595,7 +595,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
         try_cfg(c);
       }
       const KernelConfig base = cur;
-      for (int u : {2, 4, 8})
+      for (int u : {2, 3, 4, 8})
         for (int pipe = 0; pipe < 2; ++pipe) {
           KernelConfig c = base;
           c.unroll = u;

@@ -25,7 +25,7 @@ KernelConfig default_config(int kernel) {
 
 bool config_valid(int kernel, const KernelConfig& c) {
   const bool unroll_ok = kernel == 0 ? (c.unroll == 2 || c.unroll == 4 || c.unroll == 8)
-                                     : (c.unroll == 2 || c.unroll == 4);
+                                     : (c.unroll == 2 || c.unroll == 3 || c.unroll == 4);
   return unroll_ok && (c.pipeline == 0 || c.pipeline == 1) && c.span >= 1 &&
          c.span <= kMaxSpan && (c.grid_mult == 1 || c.grid_mult == 2) &&
          (c.split == 0 || c.split == 1);

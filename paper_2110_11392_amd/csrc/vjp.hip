@@ -172,12 +172,12 @@ __global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ r
   src6[6 * s + 5] = w[3 * i + 2];
 }
 
-// Register caps for more resident waves: unroll 2 fits 8 waves per SIMD, unroll
-// 4 fits 7 with a few spills at x-offset-slice boundaries (none in the pair
-// loop).  Without the caps the compiler takes 112 SGPRs and, at unroll 4,
-// 80 VGPRs: 7 and 6 waves.
+// Register caps for more resident waves: unrolls 2 and 3 fit 8 waves per SIMD,
+// unroll 4 fits 7 (unrolls 3 and 4 spill a few words at task and slice
+// boundaries, none in the pair loop).  Without the caps the compiler takes 112
+// SGPRs and, at unroll 4, 80 VGPRs: 7 and 6 waves.
 template <int kU>
-constexpr int vjp_min_waves() { return kU <= 2 ? 8 : (kU == 4 ? 7 : 1); }
+constexpr int vjp_min_waves() { return kU <= 3 ? 8 : (kU == 4 ? 7 : 1); }
 
 template <int kAcc, int kU, bool kPipe>
 __global__ __launch_bounds__(256)
@@ -336,6 +336,8 @@ static hipError_t dispatch_vjp(const KernelConfig& cfg, const DevBox* boxes, con
   const int g = cfg.grid_mult;
   switch (cfg.unroll * 2 + (cfg.pipeline ? 1 : 0)) {
     case 5: return launch_vjp_t<kAcc, 2, true>(boxes, w, off, src, perm, grad, g, s);
+    case 6: return launch_vjp_t<kAcc, 3, false>(boxes, w, off, src, perm, grad, g, s);
+    case 7: return launch_vjp_t<kAcc, 3, true>(boxes, w, off, src, perm, grad, g, s);
     case 8: return launch_vjp_t<kAcc, 4, false>(boxes, w, off, src, perm, grad, g, s);
     case 9: return launch_vjp_t<kAcc, 4, true>(boxes, w, off, src, perm, grad, g, s);
     default: return launch_vjp_t<kAcc, 2, false>(boxes, w, off, src, perm, grad, g, s);

@@ -41,7 +41,7 @@ FORWARD_SHAPES = [dict(unroll=u, pipeline=p, span=s, grid_mult=g, split=x)
                   if (s == 2 or (u == 4 and p == 0)) and (g == 1 or (u == 4 and s == 2))
                   and (x == 1 or (u == 4 and g == 1))]
 ADJOINT_SHAPES = [dict(unroll=u, pipeline=p, span=s, grid_mult=1, split=x)
-                  for u in (2, 4) for p in (0, 1) for s in (1, 2, 3) for x in (0, 1)
+                  for u in (2, 3, 4) for p in (0, 1) for s in (1, 2, 3) for x in (0, 1)
                   if (s == 2 or (u == 2 and p == 0)) and (x == 1 or (u == 2 and p == 0))]
 
 

@@ -91,29 +91,29 @@ __device__ __forceinline__ void interact_group_near(const float* c, float qx, fl
     r2[u] = __builtin_fmaf(dz[u], dz[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dx[u], dx[u], k.g)));
     m = __builtin_fminf(m, r2[u]);
   }
+  // The Newton factor for every pair; a group with a lane below near2 then
+  // replaces it by the minimum with the spline.  Only f changes inside the
+  // branch, so the accumulators are updated once, after it.
+  float f[kU], rinv[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    rinv[u] = rsq(r2[u]);
+    f[u] = (rinv[u] * rinv[u]) * rinv[u];
+  }
   if (__ballot(m < k.near2) != 0) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const float rinv = rsq(r2[u]);
-      const float rinv3 = (rinv * rinv) * rinv;
-      const float r = r2[u] * rinv;
+      const float r = r2[u] * rinv[u];
       const float spline = __builtin_fmaf(__builtin_fmaf(k.c2, r, k.c1), r, k.c0);
-      const float f = __builtin_fminf(spline, rinv3);
-      tx = __builtin_fmaf(f, dx[u], tx);
-      ty = __builtin_fmaf(f, dy[u], ty);
-      tz = __builtin_fmaf(f, dz[u], tz);
-      if (kDens) rho += __builtin_fmaxf(k.b2 - r2[u], 0.0f);
+      f[u] = __builtin_fminf(spline, f[u]);
     }
-  } else {
+  }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const float rinv = rsq(r2[u]);
-      const float f = (rinv * rinv) * rinv;
-      tx = __builtin_fmaf(f, dx[u], tx);
-      ty = __builtin_fmaf(f, dy[u], ty);
-      tz = __builtin_fmaf(f, dz[u], tz);
-      if (kDens) rho += __builtin_fmaxf(k.b2 - r2[u], 0.0f);
-    }
+  for (int u = 0; u < kU; ++u) {
+    tx = __builtin_fmaf(f[u], dx[u], tx);
+    ty = __builtin_fmaf(f[u], dy[u], ty);
+    tz = __builtin_fmaf(f[u], dz[u], tz);
+    if (kDens) rho += __builtin_fmaxf(k.b2 - r2[u], 0.0f);
   }
 }
 

@@ -76,31 +76,54 @@ struct AdjConst {
 };
 
 // kU adjoint interactions of one source group on a cell that may hold pairs
-// inside eps: the separations come first, and only if some lane has r^2 below
-// (1.1 eps)^2 (a wave-uniform vote) does the group take the branch select;
-// otherwise every pair has r > eps and the Newton expressions give the same
-// bits as adjoint<true>.
+// inside eps.  Pairs with r > eps take the Newton expressions in adjoint<true>
+// as well, so the spline select is needed only when some lane has r^2 below
+// (1.1 eps)^2 (a wave-uniform vote); either way the bits equal adjoint<true>.
 template <int kU>
 __device__ __forceinline__ void adjoint_group_near(const float* c, float qx, float qy, float qz,
                                                    float wx, float wy, float wz,
                                                    const AdjConst& k, float& gx, float& gy,
                                                    float& gz) {
+  // Only F and T change inside the branch, so the accumulators are updated
+  // once, after it, with the same operations as adjoint<>.
+  float dx[kU], dy[kU], dz[kU], vx[kU], vy[kU], vz[kU], r2[kU], rinv[kU], dv[kU], F[kU], T[kU];
   float m = 3.0e38f;
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
-    const float dx = c[6 * u] - qx, dy = c[6 * u + 1] - qy, dz = c[6 * u + 2] - qz;
-    m = __builtin_fminf(m, __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, k.g))));
+    const float* s = c + 6 * u;
+    dx[u] = s[0] - qx;
+    dy[u] = s[1] - qy;
+    dz[u] = s[2] - qz;
+    r2[u] = __builtin_fmaf(dz[u], dz[u], __builtin_fmaf(dy[u], dy[u], __builtin_fmaf(dx[u], dx[u], k.g)));
+    m = __builtin_fminf(m, r2[u]);
+    rinv[u] = rsq_v(r2[u]);
+    const float rinv2 = rinv[u] * rinv[u];
+    vx[u] = s[3] - wx;
+    vy[u] = s[4] - wy;
+    vz[u] = s[5] - wz;
+    dv[u] = __builtin_fmaf(dz[u], vz[u], __builtin_fmaf(dy[u], vy[u], dx[u] * vx[u]));
+    F[u] = rinv2 * rinv[u];
+    T[u] = (-3.0f * rinv2) * dv[u];
   }
   if (__ballot(m < k.near2) != 0) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      adjoint<true>(c + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
-                    gx, gy, gz);
-  } else {
+    for (int u = 0; u < kU; ++u) {
+      const float r = r2[u] * rinv[u];
+      const bool inner = r < k.eps;
+      const float fs = __builtin_fmaf(__builtin_fmaf(k.c2, r, k.c1), r, k.c0);
+      const float hs = __builtin_fmaf(k.hb, rinv[u], k.ha);
+      F[u] = inner ? fs : F[u];
+      T[u] = inner ? (hs * dv[u]) * __builtin_amdgcn_rcpf(fs) : T[u];
+    }
+  }
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      adjoint<false>(c + 6 * u, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g,
-                     gx, gy, gz);
+  for (int u = 0; u < kU; ++u) {
+    const float ex = __builtin_fmaf(T[u], dx[u], vx[u]);
+    const float ey = __builtin_fmaf(T[u], dy[u], vy[u]);
+    const float ez = __builtin_fmaf(T[u], dz[u], vz[u]);
+    gx = __builtin_fmaf(F[u], ex, gx);
+    gy = __builtin_fmaf(F[u], ey, gy);
+    gz = __builtin_fmaf(F[u], ez, gz);
   }
 }
 

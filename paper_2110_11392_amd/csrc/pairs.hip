@@ -166,6 +166,66 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ src3, int 
                            tz, rho);
 }
 
+// Positions [j, jend) of one lane's run starting at rb, kU per step, with the
+// next kU records requested before the current ones are used (two buffers
+// that swap roles, so no register copies between steps).
+template <int kU>
+__device__ __forceinline__ void load_run(const float* __restrict__ src3, int at, float* c) {
+#pragma unroll
+  for (int u = 0; u < 3 * kU; ++u) c[u] = src3[3 * at + u];
+}
+
+template <int kU>
+__device__ __forceinline__ void sum_lane_run(const float* __restrict__ src3, int rb, int j,
+                                             int jend, float qx, float qy, float qz,
+                                             const PairConst& k, float& tx, float& ty,
+                                             float& tz) {
+  float rho = 0.f;
+  int ng = (jend - j) / kU;  // whole groups
+  if (ng > 0) {
+    float a[3 * kU], b[3 * kU];
+    load_run<kU>(src3, rb + j, a);
+    // Every request is consumed inside the step that makes it or by the next
+    // one (the last re-reads the current group), so none is moved below the
+    // arithmetic it should overlap.
+    for (; ng >= 2; ng -= 2) {
+      load_run<kU>(src3, rb + j + kU, b);
+      __builtin_amdgcn_sched_barrier(0);
+      interact_group<kU, false, false>(a, qx, qy, qz, k, tx, ty, tz, rho);
+      load_run<kU>(src3, rb + j + (ng >= 3 ? 2 * kU : kU), a);
+      __builtin_amdgcn_sched_barrier(0);
+      interact_group<kU, false, false>(b, qx, qy, qz, k, tx, ty, tz, rho);
+      j += 2 * kU;
+    }
+    if (ng == 1) {
+      interact_group<kU, false, false>(a, qx, qy, qz, k, tx, ty, tz, rho);
+      j += kU;
+    }
+  }
+  for (; j < jend; ++j)
+    interact<false, false>(src3[3 * (rb + j)], src3[3 * (rb + j) + 1], src3[3 * (rb + j) + 2], qx,
+                           qy, qz, k, tx, ty, tz, rho);
+}
+
+// The two edge cells of a two-cell item (za, za + 1): lanes of the lower
+// sink cell need the cell R below it and lanes of the upper sink cell the cell
+// R above it, and neither set needs the other's.  Both runs are far cells
+// (Newtonian for Eq. 3, or the Plummer law), so the wave steps through them
+// together, each lane reading its own run at per-lane addresses: the longer
+// run's length instead of the sum of both.  This sums the positions [j0, j1)
+// of the lane's run (rb, rn); m = the shorter run's length, so [0, m) is
+// valid in every lane and the rest only in the lanes of the longer run.
+template <int kU>
+__device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3, int rb, int rn,
+                                              int m, int j0, int j1, float qx, float qy,
+                                              float qz, const PairConst& k, float& tx, float& ty,
+                                              float& tz) {
+  const int a_end = m < j1 ? m : j1;
+  if (j0 < a_end) sum_lane_run<kU>(src3, rb, j0, a_end, qx, qy, qz, k, tx, ty, tz);
+  const int b_beg = j0 > a_end ? j0 : a_end;
+  if (rn > m && b_beg < j1) sum_lane_run<kU>(src3, rb, b_beg, j1, qx, qy, qz, k, tx, ty, tz);
+}
+
 // Packed 12-byte source records (x, y, z) from the binned float4 offsets.
 __global__ __launch_bounds__(256) void k_pack_sources(const float4* __restrict__ rel, int64_t n,
                                                       float* __restrict__ src3) {
@@ -244,6 +304,11 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
     const bool active = s >= 0;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) p = rel[s];
+    // Two-cell items take their edge cells as paired per-lane runs when those
+    // cells are far (R >= 2, no spline) and add no density (sum_edge_runs).
+    const bool pair_edges = zb == za + 1 && R >= 2 && far_mode != kFarNone &&
+                            (!kDens || dens_far);
+    const bool upper = lane_z == zb;
 
     // (A, E): the sink's sum; (a, e): the current x-offset slice (SINGLE keeps
     // one running accumulator in a and never folds).
@@ -260,6 +325,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
         const int col = cbase + (sx * K + sy) * K;
         const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
         for (int zu = za - R; zu <= zb + R; ++zu) {
+          if (pair_edges && (zu == za - R || zu == zb + R)) continue;
           const int sz = wrap1(zu, K);
           const int beg = uniform(off[col + sz]), end = uniform(off[col + sz + 1]);
           if (beg == end) continue;
@@ -297,6 +363,37 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
                   two_sum_fold(ax, ex, tx);
                   two_sum_fold(ay, ey, ty);
                   two_sum_fold(az, ez, tz);
+                }
+              }
+            }
+          }
+        }
+        if (pair_edges) {
+          const int zl = wrap1(za - R, K), zh = wrap1(zb + R, K);
+          const int bl = uniform(off[col + zl]), nl = uniform(off[col + zl + 1]) - bl;
+          const int bh = uniform(off[col + zh]), nh = uniform(off[col + zh + 1]) - bh;
+          const int nmax = nl > nh ? nl : nh, m = nl < nh ? nl : nh;
+          if (nmax > 0) {
+            left -= nl + nh;
+            set_wave_priority(left);
+            if (active) {
+              const int rb = upper ? bh : bl, rn = upper ? nh : nl;
+              const float qz = p.z - (float)(upper ? R : -R);
+              if (kCount) npairs += rn;
+              if (kAcc == kAccSingle) {
+                sum_edge_runs<kU>(src3, rb, rn, m, 0, nmax, qx, qy, qz, kc, ax, ay, az);
+              } else {
+                for (int cb = 0; cb < nmax; cb += kChunk) {
+                  const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
+                  float tx = 0.f, ty = 0.f, tz = 0.f;
+                  sum_edge_runs<kU>(src3, rb, rn, m, cb, ce, qx, qy, qz, kc, tx, ty, tz);
+                  if (kAcc == kAccChunked) {
+                    ax += tx; ay += ty; az += tz;
+                  } else {
+                    two_sum_fold(ax, ex, tx);
+                    two_sum_fold(ay, ey, ty);
+                    two_sum_fold(az, ez, tz);
+                  }
                 }
               }
             }

@@ -53,6 +53,10 @@ def small_boxes():
                                       synth.uniform(1500, 11)).astype(np.float32),
                                      1.0, 8, 2, 1 / 2000)],
         "box_3p7_K11": [synth.Box(synth.uniform(4000, 12, 3.7), 3.7, 11, 2, 3.7 / 640)],
+        # K = 2R + 1: the cell R below an item's lower cell is the cell R above
+        # its upper cell, so the paired edge runs of two-cell items coincide
+        "clustered_K5_edges": [synth.Box(synth.clustered(3000, 8, 5, 18), 1.0, 5, 2, 1 / 400)],
+        "clustered_K6_edges": [synth.Box(synth.clustered(3500, 8, 6, 19), 1.0, 6, 2, 1 / 450)],
         # softening just below / above half a cell: the Newton-only path for
         # cells two apart is on / off
         "soft_0p45_cell": [synth.Box(synth.clustered(3000, 10, 8, 16), 1.0, 8, 2,

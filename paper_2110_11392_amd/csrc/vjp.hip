@@ -178,6 +178,74 @@ __device__ __forceinline__ void sum_adjoint(const float* __restrict__ src6, int 
   }
 }
 
+// The two edge cells of a two-cell item (za, za + 1): lanes of the lower
+// sink cell need the cell R below it and lanes of the upper sink cell the cell
+// R above it, and neither set needs the other's.  Both are far cells (every
+// pair has r > eps, or the Plummer law), so the wave steps through the two
+// runs together and pays the longer run's length instead of the sum of both.
+// Per chunk of kChunk positions the wave stages both runs' records in its own
+// LDS slot (lane l copies position l of each run, coalesced), then every lane
+// reads its own run's records from there: two distinct LDS addresses per read,
+// served as broadcasts.  (Per-lane global loads of the same records took the
+// L1 address path for 24 cycles per record and wave.)  Lanes of the shorter
+// run stop at its end; the sums are folded per chunk like a cell's.
+constexpr int kEdgeRec = 6;
+
+template <int kAcc>
+__device__ __forceinline__ void adjoint_edge_runs(const float* __restrict__ src6,
+                                                  float* __restrict__ slot, int lane, bool upper,
+                                                  int bl, int nl, int bh, int nh, float qx,
+                                                  float qy, float qz, float wx, float wy,
+                                                  float wz, const AdjConst& k, float& gx,
+                                                  float& gy, float& gz, float& ex, float& ey,
+                                                  float& ez) {
+  const int nmax = nl > nh ? nl : nh;
+  const int rn = upper ? nh : nl;
+  const float* mine = slot + (upper ? kChunk * kEdgeRec : 0);
+  for (int cb = 0; cb < nmax; cb += kChunk) {
+    const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
+    if (cb + lane < nl) {
+#pragma unroll
+      for (int c = 0; c < kEdgeRec; ++c) slot[kEdgeRec * lane + c] = src6[kEdgeRec * (bl + cb + lane) + c];
+    }
+    if (cb + lane < nh) {
+#pragma unroll
+      for (int c = 0; c < kEdgeRec; ++c)
+        slot[kChunk * kEdgeRec + kEdgeRec * lane + c] = src6[kEdgeRec * (bh + cb + lane) + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int n = (rn < ce ? rn : ce) - cb;  // this lane's positions in the chunk
+    float tx = 0.f, ty = 0.f, tz = 0.f;
+    int j = 0;
+    for (; j + 2 <= n; j += 2) {
+      float c2[2 * kEdgeRec];
+#pragma unroll
+      for (int u = 0; u < 2 * kEdgeRec; ++u) c2[u] = mine[kEdgeRec * j + u];
+      adjoint<false>(c2, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, tx,
+                     ty, tz);
+      adjoint<false>(c2 + kEdgeRec, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps,
+                     k.g, tx, ty, tz);
+    }
+    if (j < n) {
+      float c1[kEdgeRec];
+#pragma unroll
+      for (int u = 0; u < kEdgeRec; ++u) c1[u] = mine[kEdgeRec * j + u];
+      adjoint<false>(c1, qx, qy, qz, wx, wy, wz, k.c0, k.c1, k.c2, k.ha, k.hb, k.eps, k.g, tx,
+                     ty, tz);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (n > 0) {
+      if (kAcc == kAccSingle || kAcc == kAccChunked) {
+        gx += tx; gy += ty; gz += tz;
+      } else {
+        two_sum_fold(gx, ex, tx);
+        two_sum_fold(gy, ey, ty);
+        two_sum_fold(gz, ez, tz);
+      }
+    }
+  }
+}
+
 // Packed source records (rel_s, w_perm[s]) per sorted slot, 6 floats each.
 __global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ rel,
                                                     const int32_t* __restrict__ perm,
@@ -211,6 +279,9 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     const int32_t* __restrict__ perm, float* __restrict__ grad, float* __restrict__ partial,
     int n_static) {
   const int lane = threadIdx.x & 63;
+  // this wave's staging slot for the paired edge runs (two runs of kChunk records)
+  __shared__ float edge_lds[4][2 * kChunk * kEdgeRec];
+  float* const edge_slot = edge_lds[threadIdx.x >> 6];
   const int n_tasks = uni(ctrl[kCtrlNTasks]);
   const int n_whole = uni(ctrl[kCtrlNWhole]);
   const int n_split = uni(ctrl[kCtrlNSplit]);
@@ -250,6 +321,10 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     for (int z = za; z < zb; ++z)
       if (s >= uni(off[pencil0 + z + 1])) lane_z = z + 1;
     const bool active = s >= 0;
+    // Two-cell items take their edge cells as paired runs when those cells
+    // are far (R >= 2, no spline; adjoint_edge_runs).
+    const bool pair_edges = zb == za + 1 && R >= 2 && far_mode != kFarNone;
+    const bool upper = lane_z == zb;
     float px = 0.f, py = 0.f, pz = 0.f, wkx = 0.f, wky = 0.f, wkz = 0.f;
     if (active) {
       px = src6[6 * s + 0];
@@ -274,6 +349,7 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
         const int col = cbase + (sx * K + sy) * K;
         const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
         for (int zu = za - R; zu <= zb + R; ++zu) {
+          if (pair_edges && (zu == za - R || zu == zb + R)) continue;
           const int sz = wrap1_v(zu, K);
           const int beg = uni(off[col + sz]), end = uni(off[col + sz + 1]);
           if (beg == end) continue;
@@ -310,6 +386,20 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
                 }
               }
             }
+          }
+        }
+        if (pair_edges) {
+          const int zl = wrap1_v(za - R, K), zh = wrap1_v(zb + R, K);
+          const int bl = uni(off[col + zl]), nl = uni(off[col + zl + 1]) - bl;
+          const int bh = uni(off[col + zh]), nh = uni(off[col + zh + 1]) - bh;
+          if (nl + nh > 0) {
+            left -= nl + nh;
+            set_wave_priority(left);
+            // every lane takes part (each stages records); inactive lanes'
+            // sums are never written
+            adjoint_edge_runs<kAcc>(src6, edge_slot, lane, upper, bl, nl, bh, nh, qx, qy,
+                                    pz - (float)(upper ? R : -R), wkx, wky, wkz, kc, gx, gy, gz,
+                                    ex, ey, ez);
           }
         }
       }

@@ -166,64 +166,60 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ src3, int 
                            tz, rho);
 }
 
-// Positions [j, jend) of one lane's run starting at rb, kU per step, with the
-// next kU records requested before the current ones are used (two buffers
-// that swap roles, so no register copies between steps).
-template <int kU>
-__device__ __forceinline__ void load_run(const float* __restrict__ src3, int at, float* c) {
-#pragma unroll
-  for (int u = 0; u < 3 * kU; ++u) c[u] = src3[3 * at + u];
-}
-
-template <int kU>
-__device__ __forceinline__ void sum_lane_run(const float* __restrict__ src3, int rb, int j,
-                                             int jend, float qx, float qy, float qz,
-                                             const PairConst& k, float& tx, float& ty,
-                                             float& tz) {
-  float rho = 0.f;
-  int ng = (jend - j) / kU;  // whole groups
-  if (ng > 0) {
-    float a[3 * kU], b[3 * kU];
-    load_run<kU>(src3, rb + j, a);
-    // Every request is consumed inside the step that makes it or by the next
-    // one (the last re-reads the current group), so none is moved below the
-    // arithmetic it should overlap.
-    for (; ng >= 2; ng -= 2) {
-      load_run<kU>(src3, rb + j + kU, b);
-      __builtin_amdgcn_sched_barrier(0);
-      interact_group<kU, false, false>(a, qx, qy, qz, k, tx, ty, tz, rho);
-      load_run<kU>(src3, rb + j + (ng >= 3 ? 2 * kU : kU), a);
-      __builtin_amdgcn_sched_barrier(0);
-      interact_group<kU, false, false>(b, qx, qy, qz, k, tx, ty, tz, rho);
-      j += 2 * kU;
-    }
-    if (ng == 1) {
-      interact_group<kU, false, false>(a, qx, qy, qz, k, tx, ty, tz, rho);
-      j += kU;
-    }
-  }
-  for (; j < jend; ++j)
-    interact<false, false>(src3[3 * (rb + j)], src3[3 * (rb + j) + 1], src3[3 * (rb + j) + 2], qx,
-                           qy, qz, k, tx, ty, tz, rho);
-}
-
 // The two edge cells of a two-cell item (za, za + 1): lanes of the lower
 // sink cell need the cell R below it and lanes of the upper sink cell the cell
-// R above it, and neither set needs the other's.  Both runs are far cells
-// (Newtonian for Eq. 3, or the Plummer law), so the wave steps through them
-// together, each lane reading its own run at per-lane addresses: the longer
-// run's length instead of the sum of both.  This sums the positions [j0, j1)
-// of the lane's run (rb, rn); m = the shorter run's length, so [0, m) is
-// valid in every lane and the rest only in the lanes of the longer run.
-template <int kU>
-__device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3, int rb, int rn,
-                                              int m, int j0, int j1, float qx, float qy,
-                                              float qz, const PairConst& k, float& tx, float& ty,
-                                              float& tz) {
-  const int a_end = m < j1 ? m : j1;
-  if (j0 < a_end) sum_lane_run<kU>(src3, rb, j0, a_end, qx, qy, qz, k, tx, ty, tz);
-  const int b_beg = j0 > a_end ? j0 : a_end;
-  if (rn > m && b_beg < j1) sum_lane_run<kU>(src3, rb, b_beg, j1, qx, qy, qz, k, tx, ty, tz);
+// R above it, and neither set needs the other's.  Both are far cells
+// (Newtonian for Eq. 3, or the Plummer law), so the wave steps through the two
+// runs together and pays the longer run's length instead of the sum of both.
+// Per chunk of kChunk positions the wave stages both runs' records in its own
+// LDS slot (lane l copies position l of each run, coalesced), then every lane
+// reads its own run's records from there: two distinct LDS addresses per read,
+// served as broadcasts.  (Per-lane global loads of the same records took the
+// L1 address path for 16 cycles per record and wave.)  Lanes of the shorter
+// run stop at its end; the sums are folded per chunk like a cell's.
+template <int kAcc, int kU>
+__device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3,
+                                              float* __restrict__ slot, int lane, bool upper,
+                                              int bl, int nl, int bh, int nh, float qx, float qy,
+                                              float qz, const PairConst& k, float& ax, float& ay,
+                                              float& az, float& ex, float& ey, float& ez) {
+  const int nmax = nl > nh ? nl : nh;
+  const int rn = upper ? nh : nl;
+  const float* mine = slot + (upper ? 3 * kChunk : 0);
+  for (int cb = 0; cb < nmax; cb += kChunk) {
+    const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
+    if (cb + lane < nl) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) slot[3 * lane + c] = src3[3 * (bl + cb + lane) + c];
+    }
+    if (cb + lane < nh) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) slot[3 * kChunk + 3 * lane + c] = src3[3 * (bh + cb + lane) + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int n = (rn < ce ? rn : ce) - cb;  // this lane's positions in the chunk
+    float tx = 0.f, ty = 0.f, tz = 0.f, rho = 0.f;
+    int j = 0;
+    for (; j + kU <= n; j += kU) {
+      float c[3 * kU];
+#pragma unroll
+      for (int u = 0; u < 3 * kU; ++u) c[u] = mine[3 * j + u];
+      interact_group<kU, false, false>(c, qx, qy, qz, k, tx, ty, tz, rho);
+    }
+    for (; j < n; ++j)
+      interact<false, false>(mine[3 * j], mine[3 * j + 1], mine[3 * j + 2], qx, qy, qz, k, tx, ty,
+                             tz, rho);
+    __builtin_amdgcn_wave_barrier();
+    if (n > 0) {
+      if (kAcc == kAccSingle || kAcc == kAccChunked) {
+        ax += tx; ay += ty; az += tz;
+      } else {
+        two_sum_fold(ax, ex, tx);
+        two_sum_fold(ay, ey, ty);
+        two_sum_fold(az, ez, tz);
+      }
+    }
+  }
 }
 
 // Packed 12-byte source records (x, y, z) from the binned float4 offsets.
@@ -255,6 +251,9 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
     float* __restrict__ dens_out, float* __restrict__ partial,
     unsigned long long* __restrict__ pair_count, int n_static) {
   const int lane = threadIdx.x & 63;
+  // this wave's staging slot for the paired edge runs (two runs of kChunk records)
+  __shared__ float edge_lds[4][2 * kChunk * 3];
+  float* const edge_slot = edge_lds[threadIdx.x >> 6];
   const int n_tasks = uniform(ctrl[kCtrlNTasks]);
   const int n_whole = uniform(ctrl[kCtrlNWhole]);
   const int n_split = uniform(ctrl[kCtrlNSplit]);
@@ -304,8 +303,8 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
     const bool active = s >= 0;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) p = rel[s];
-    // Two-cell items take their edge cells as paired per-lane runs when those
-    // cells are far (R >= 2, no spline) and add no density (sum_edge_runs).
+    // Two-cell items take their edge cells as paired runs when those cells are
+    // far (R >= 2, no spline) and add no density (sum_edge_runs).
     const bool pair_edges = zb == za + 1 && R >= 2 && far_mode != kFarNone &&
                             (!kDens || dens_far);
     const bool upper = lane_z == zb;
@@ -372,31 +371,14 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
           const int zl = wrap1(za - R, K), zh = wrap1(zb + R, K);
           const int bl = uniform(off[col + zl]), nl = uniform(off[col + zl + 1]) - bl;
           const int bh = uniform(off[col + zh]), nh = uniform(off[col + zh + 1]) - bh;
-          const int nmax = nl > nh ? nl : nh, m = nl < nh ? nl : nh;
-          if (nmax > 0) {
+          if (nl + nh > 0) {
             left -= nl + nh;
             set_wave_priority(left);
-            if (active) {
-              const int rb = upper ? bh : bl, rn = upper ? nh : nl;
-              const float qz = p.z - (float)(upper ? R : -R);
-              if (kCount) npairs += rn;
-              if (kAcc == kAccSingle) {
-                sum_edge_runs<kU>(src3, rb, rn, m, 0, nmax, qx, qy, qz, kc, ax, ay, az);
-              } else {
-                for (int cb = 0; cb < nmax; cb += kChunk) {
-                  const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
-                  float tx = 0.f, ty = 0.f, tz = 0.f;
-                  sum_edge_runs<kU>(src3, rb, rn, m, cb, ce, qx, qy, qz, kc, tx, ty, tz);
-                  if (kAcc == kAccChunked) {
-                    ax += tx; ay += ty; az += tz;
-                  } else {
-                    two_sum_fold(ax, ex, tx);
-                    two_sum_fold(ay, ey, ty);
-                    two_sum_fold(az, ez, tz);
-                  }
-                }
-              }
-            }
+            if (kCount && active) npairs += upper ? nh : nl;
+            // every lane takes part (each stages records); inactive lanes'
+            // sums are never written
+            sum_edge_runs<kAcc, kU>(src3, edge_slot, lane, upper, bl, nl, bh, nh, qx, qy,
+                                    p.z - (float)(upper ? R : -R), kc, ax, ay, az, ex, ey, ez);
           }
         }
       }

@@ -372,7 +372,7 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
           const int bl = uniform(off[col + zl]), nl = uniform(off[col + zl + 1]) - bl;
           const int bh = uniform(off[col + zh]), nh = uniform(off[col + zh + 1]) - bh;
           if (nl + nh > 0) {
-            left -= nl + nh;
+            left -= nl > nh ? nl : nh;
             set_wave_priority(left);
             if (kCount && active) npairs += upper ? nh : nl;
             // every lane takes part (each stages records); inactive lanes'

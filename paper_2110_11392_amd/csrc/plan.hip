@@ -93,7 +93,9 @@ __device__ __forceinline__ int64_t column_range_count(const int32_t* __restrict_
   return total;
 }
 
-// Cost of an item = sources in the (2R+1)^2 columns over z in [za-R, zb+R].
+// Cost of an item = source visits of its wave: the sources in the (2R+1)^2
+// columns over z in [za-R, zb+R], with a two-cell item's paired far edge
+// cells counted once at the longer one's length.
 __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ boxes,
                                                    const int4* __restrict__ items,
                                                    const int32_t* __restrict__ n_items_ptr,
@@ -114,6 +116,8 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
     const DevBox& B = boxes[it.x & 0xffff];
     const int K = B.K, R = B.R;
     const int cx = it.y & 0xffff, cy = it.y >> 16, za = it.z & 0xffff, zb = it.z >> 16;
+    // two-cell items walk their far edge cells together: the longer one counts
+    const bool paired = zb == za + 1 && R >= 2 && B.far_mode != kFarNone;
     int64_t cost = 0;
     for (int ox = -R; ox <= R; ++ox) {
       int x = cx + ox;
@@ -123,7 +127,14 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
         int y = cy + oy;
         y += y < 0 ? K : 0;
         y -= y >= K ? K : 0;
-        cost += column_range_count(off, B.cell_base + (x * K + y) * K, K, za - R, zb + R);
+        const int col = B.cell_base + (x * K + y) * K;
+        if (paired) {
+          const int64_t lo = column_range_count(off, col, K, za - R, za - R);
+          const int64_t hi = column_range_count(off, col, K, zb + R, zb + R);
+          cost += column_range_count(off, col, K, za - R + 1, zb + R - 1) + (lo > hi ? lo : hi);
+        } else {
+          cost += column_range_count(off, col, K, za - R, zb + R);
+        }
       }
     }
     const int lg = cost > 0 ? 63 - __clzll((unsigned long long)cost) : 0;

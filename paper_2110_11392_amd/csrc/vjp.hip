@@ -393,7 +393,7 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
           const int bl = uni(off[col + zl]), nl = uni(off[col + zl + 1]) - bl;
           const int bh = uni(off[col + zh]), nh = uni(off[col + zh + 1]) - bh;
           if (nl + nh > 0) {
-            left -= nl + nh;
+            left -= nl > nh ? nl : nh;
             set_wave_priority(left);
             // every lane takes part (each stages records); inactive lanes'
             // sums are never written

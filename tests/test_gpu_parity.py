@@ -57,6 +57,14 @@ def small_boxes():
         # its upper cell, so the paired edge runs of two-cell items coincide
         "clustered_K5_edges": [synth.Box(synth.clustered(3000, 8, 5, 18), 1.0, 5, 2, 1 / 400)],
         "clustered_K6_edges": [synth.Box(synth.clustered(3500, 8, 6, 19), 1.0, 6, 2, 1 / 450)],
+        # 3000 particles in cell (4, 4, 1) beside 8 per cell elsewhere: two-cell
+        # items of pencil (4, 4) pair a 3000-particle edge run with an 8-particle
+        # one (47 chunks, one lane set active after the first)
+        "edge_crowd_K8": [synth.Box(np.concatenate([
+            synth.uniform(4096, 20),
+            (np.array([4.5, 4.5, 1.5], np.float32) / np.float32(8) +
+             np.float32(0.08) * (synth.uniform(3000, 21) - np.float32(0.5))).astype(np.float32)]),
+            1.0, 8, 2, 1 / 800)],
         # softening just below / above half a cell: the Newton-only path for
         # cells two apart is on / off
         "soft_0p45_cell": [synth.Box(synth.clustered(3000, 10, 8, 16), 1.0, 8, 2,
@@ -289,6 +297,28 @@ def test_vjp_small_all_modes(nfmod):
         rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
         say(f"  {accumulation}: relative error {rel:.3g}")
         assert rel <= VJP_TOL
+
+
+@pytest.mark.parametrize("name", ["edge_crowd_K8", "clustered_K5_edges", "clustered_K6_edges"])
+def test_vjp_paired_edge_runs(nfmod, name):
+    """Adjoint on boxes whose two-cell items pair edge runs of very different
+    lengths (a crowded cell against sparse ones) or where the two edge cells
+    are one cell (K = 2R + 1), in every accumulation mode."""
+    boxes = small_boxes()[name]
+    b = boxes[0]
+    say(f"[vjp] {name}")
+    nf = make_nf(nfmod, boxes)
+    bd = nf.bin(upload(boxes))
+    w = synth.gaussian_weights(b.n, 98)
+    ref = oracle.vjp(b.pos, w, b.box, b.cpd, b.radius, b.eps_plummer)
+    for accumulation in ("compensated", "chunked", "single"):
+        g = nf.forces_vjp(bd, torch.from_numpy(w).cuda(), accumulation).cpu().numpy()
+        rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        st = err_stats(frac_err(g, ref))
+        say(f"  {accumulation}: relative error {rel:.3g} per particle {st}")
+        assert rel <= VJP_TOL
+        if accumulation != "single":
+            assert st["median"] <= 1e-5
 
 
 @pytest.mark.parametrize("name", ["one_cell_crowd", "soft_0p60_cell", "clustered_K9_R1"])

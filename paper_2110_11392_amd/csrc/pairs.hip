@@ -14,6 +14,9 @@
 //     so they arrive through the scalar cache into SGPRs and feed every lane's
 //     VALU instruction directly -- every lane sees the same source at the same
 //     time, so no LDS staging, barrier or broadcast read is needed;
+//   * the exception is an item whose sinks lie in two cells: its two far edge
+//     cells (each needed by one of the two lane sets) are walked together,
+//     staged per 64-position chunk in the wave's own LDS slot;
 //   * the periodic wrap never reaches the arithmetic: a source cell's integer
 //     offset o from the sink's cell is folded into the sink (q = p - o) once per
 //     source cell, and d = s - q uses only FP32 cell-relative coordinates;

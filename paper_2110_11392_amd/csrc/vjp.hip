@@ -12,7 +12,8 @@
 //
 // Same traversal and work items as the forward kernel; each source carries
 // (position, cotangent) as a packed 24-byte record that wave-uniform scalar
-// loads bring into SGPRs.
+// loads bring into SGPRs (and, for the paired edge cells of two-cell items,
+// the wave's LDS slot).
 #include "nf_internal.h"
 
 namespace anf {

@@ -128,12 +128,14 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
         y += y < 0 ? K : 0;
         y -= y >= K ? K : 0;
         const int col = B.cell_base + (x * K + y) * K;
-        if (paired) {
-          const int64_t lo = column_range_count(off, col, K, za - R, za - R);
-          const int64_t hi = column_range_count(off, col, K, zb + R, zb + R);
-          cost += column_range_count(off, col, K, za - R + 1, zb + R - 1) + (lo > hi ? lo : hi);
-        } else {
-          cost += column_range_count(off, col, K, za - R, zb + R);
+        cost += column_range_count(off, col, K, za - R, zb + R);
+        if (paired) {  // the shorter edge run costs nothing extra
+          int zl = za - R, zh = zb + R;
+          zl += zl < 0 ? K : 0;
+          zh -= zh >= K ? K : 0;
+          const int lo = off[col + zl + 1] - off[col + zl];
+          const int hi = off[col + zh + 1] - off[col + zh];
+          cost -= lo < hi ? lo : hi;
         }
       }
     }

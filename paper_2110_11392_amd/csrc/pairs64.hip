@@ -76,6 +76,35 @@ __device__ __forceinline__ void sum64(const float* __restrict__ src3, int beg, i
     interact64<kNear>(src3[3 * j], src3[3 * j + 1], src3[3 * j + 2], qx, qy, qz, k, tx, ty, tz);
 }
 
+// The two far edge cells of a two-cell item walked together (the forward FP32
+// kernel's scheme): per chunk of kChunk positions the wave stages both runs in
+// its own LDS slot, then each lane sums its own run's records from there.
+__device__ __forceinline__ void sum64_edge_runs(const float* __restrict__ src3,
+                                                float* __restrict__ slot, int lane, bool upper,
+                                                int bl, int nl, int bh, int nh, double qx,
+                                                double qy, double qz, const Const64& k,
+                                                double& tx, double& ty, double& tz) {
+  const int nmax = nl > nh ? nl : nh;
+  const int rn = upper ? nh : nl;
+  const float* mine = slot + (upper ? 3 * kChunk : 0);
+  for (int cb = 0; cb < nmax; cb += kChunk) {
+    const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
+    if (cb + lane < nl) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) slot[3 * lane + c] = src3[3 * (bl + cb + lane) + c];
+    }
+    if (cb + lane < nh) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) slot[3 * kChunk + 3 * lane + c] = src3[3 * (bh + cb + lane) + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int n = (rn < ce ? rn : ce) - cb;
+    for (int j = 0; j < n; ++j)
+      interact64<false>(mine[3 * j], mine[3 * j + 1], mine[3 * j + 2], qx, qy, qz, k, tx, ty, tz);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Capped at 64 VGPRs and 80 SGPRs (no spills) for 8 resident waves per SIMD
 // instead of the compiler's 7.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pair_forward_f64(
@@ -86,6 +115,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const float* __restrict__ src3, const int32_t* __restrict__ perm,
     double* __restrict__ acc_out, int n_static) {
   const int lane = threadIdx.x & 63;
+  __shared__ float edge_lds[4][2 * kChunk * 3];  // per wave: two staged runs
+  float* const edge_slot = edge_lds[threadIdx.x >> 6];
   const int n_tasks = uni64(ctrl[kCtrlNTasks]);
   bool first = true;
   while (true) {
@@ -119,6 +150,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const bool active = s >= 0;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) p = rel[s];
+    // two-cell items walk their two far edge cells together (sum64_edge_runs)
+    const bool pair_edges = zb == za + 1 && R >= 2 && far_mode != kFarNone;
+    const bool upper = lane_z == zb;
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int ox = -R; ox <= R; ++ox) {
       const int sx = wrap64(cx + ox, K);
@@ -129,6 +163,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         const int col = cbase + (sx * K + sy) * K;
         const bool col_near = ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1;
         for (int zu = za - R; zu <= zb + R; ++zu) {
+          if (pair_edges && (zu == za - R || zu == zb + R)) continue;
           const int sz = wrap64(zu, K);
           const int beg = uni64(off[col + sz]), end = uni64(off[col + sz + 1]);
           if (beg == end) continue;
@@ -143,6 +178,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
               sum64<true>(src3, beg, end, qx, qy, qz, kc, ax, ay, az);
             else
               sum64<false>(src3, beg, end, qx, qy, qz, kc, ax, ay, az);
+          }
+        }
+        if (pair_edges) {
+          const int zl = wrap64(za - R, K), zh = wrap64(zb + R, K);
+          const int bl = uni64(off[col + zl]), nl = uni64(off[col + zl + 1]) - bl;
+          const int bh = uni64(off[col + zh]), nh = uni64(off[col + zh + 1]) - bh;
+          if (nl + nh > 0) {
+            left -= nl > nh ? nl : nh;
+            set_wave_priority(left);
+            // every lane takes part (each stages records); inactive lanes'
+            // sums are never written
+            sum64_edge_runs(src3, edge_slot, lane, upper, bl, nl, bh, nh, qx, qy,
+                            (double)p.z - (double)(upper ? R : -R), kc, ax, ay, az);
           }
         }
       }

@@ -41,11 +41,18 @@ def dyadic(pos):
 
 
 @pytest.mark.parametrize("law", ["spline", "plummer"])
-@pytest.mark.parametrize("case", ["clustered_K8", "uniform_K16_R1", "soft_0p6_cell"])
+@pytest.mark.parametrize("case", ["clustered_K8", "uniform_K16_R1", "soft_0p6_cell",
+                                  "edge_crowd_K8"])
 def test_fp64_matches_oracle_to_fp64_rounding(anf, law, case):
+    # edge_crowd_K8: 3000 particles in cell (4, 4, 1) beside 8 per cell, so
+    # two-cell items pair a long edge run with a short one
+    crowd = np.concatenate([synth.uniform(4096, 504),
+                            np.array([4.5, 4.5, 1.5]) / 8 +
+                            0.08 * (synth.uniform(3000, 505).astype(np.float64) - 0.5)])
     spec = {"clustered_K8": (synth.clustered(6000, 10, 8, 501), 8, 2, 1 / 700),
             "uniform_K16_R1": (synth.uniform(8000, 502), 16, 1, 1 / 1000),
-            "soft_0p6_cell": (synth.clustered(4000, 8, 8, 503), 8, 2, 0.6 / 8 / 2.16)}[case]
+            "soft_0p6_cell": (synth.clustered(4000, 8, 8, 503), 8, 2, 0.6 / 8 / 2.16),
+            "edge_crowd_K8": (crowd, 8, 2, 1 / 800)}[case]
     pos, K, R, eps = spec
     pos = dyadic(pos)
     say(f"[fp64] {case} {law}")

@@ -179,7 +179,8 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ src3, int 
 // reads its own run's records from there: two distinct LDS addresses per read,
 // served as broadcasts.  (Per-lane global loads of the same records took the
 // L1 address path for 16 cycles per record and wave.)  Lanes of the shorter
-// run stop at its end; the sums are folded per chunk like a cell's.
+// run stop at its end; the sums are folded per chunk like a cell's (the single
+// and chunked modes add the chunk's sum to the running accumulator).
 template <int kAcc, int kU>
 __device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3,
                                               float* __restrict__ slot, int lane, bool upper,

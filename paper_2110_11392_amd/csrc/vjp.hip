@@ -266,9 +266,10 @@ __global__ __launch_bounds__(256) void k_gather_src(const float4* __restrict__ r
 }
 
 // Register caps for more resident waves: unrolls 2 and 3 fit 8 waves per SIMD,
-// unroll 4 fits 7 (unrolls 3 and 4 spill a few words at task and slice
-// boundaries, none in the pair loop).  Without the caps the compiler takes 112
-// SGPRs and, at unroll 4, 80 VGPRs: 7 and 6 waves.
+// unroll 4 fits 7.  Unroll 2 does not spill; unroll 3 spills 56 bytes at task
+// and column boundaries, unroll 4 76 bytes, with one reload in the single-record
+// tail of an edge-run chunk.  Without the caps the compiler takes 112 SGPRs
+// and, at unroll 4, 80 VGPRs: 7 and 6 waves.
 template <int kU>
 constexpr int vjp_min_waves() { return kU <= 3 ? 8 : (kU == 4 ? 7 : 1); }
 

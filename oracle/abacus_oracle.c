@@ -23,7 +23,7 @@
  *                  frozen), used to pin oracle_vjp.
  *   oracle_density the apodized top-hat density estimate over the same near
  *                  field (Sec. 3.4.4).
- *   oracle_kick_drift  one leapfrog kick and drift (Sec. 2.1) with the per-cell
+ *   oracle_kick_drift  one leapfrog kick and drift (Sec. 3.1) with the per-cell
  *                  rms velocity and maximum acceleration of the time-step
  *                  criterion, Eq. 1; oracle_timestep evaluates Eq. 1.
  *   oracle_multipoles  the cell multipoles of Eq. 4 in the complete basis of
@@ -481,6 +481,14 @@ static int64_t complete_index(int p, int a, int b, int c)
     return -1;
 }
 
+/* x^e for an integer e >= 0 by e successive multiplications (x^0 = 1). */
+static double int_power(double x, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r = r * x;
+    return r;
+}
+
 static double factorial(int n)
 {
     double f = 1.0;
@@ -498,8 +506,9 @@ static double binomial(int n, int k)
  * Eq. 4, M^{a,b,c} = sum_q x_q^a y_q^b z_q^c over the particles q of the cell,
  * with (x_q, y_q, z_q) the particle's displacement from the cell centre in box
  * units: its stored FP32 cell-relative offset (as oracle_bin makes it) times
- * the cell width w = L/K.  The sum is formed in FP64 with the powers built by
- * repeated multiplication, as the order loop of Eq. 4 reads.
+ * the cell width w = L/K.  Each summand is formed in FP64 straight from the
+ * definition: the three integer powers x^a, y^b, z^c are computed separately
+ * (int_power) and multiplied, then added to the term's sum.
  *
  * reduced != 0 instead returns (p+1)^2 values per cell: for c0 in {0, 1} and
  * a + b + c0 <= p (same enumeration order, c restricted to {0, 1}),
@@ -527,6 +536,22 @@ int oracle_multipoles(int64_t n, const float *pos, double L, int32_t K, int32_t 
     grid_t g;
     int rc = grid_build(&g, n, pos, L, K, rel);
     if (rc) { free(M); free(rel); return rc; }
+    /* the (a, b, c) of every complete-basis term, in output order */
+    int *ta = (int *)malloc(sizeof(int) * (size_t)cml);
+    int *tb = (int *)malloc(sizeof(int) * (size_t)cml);
+    int *tc = (int *)malloc(sizeof(int) * (size_t)cml);
+    if (!ta || !tb || !tc) {
+        free(ta); free(tb); free(tc); free(M); free(rel); grid_free(&g);
+        return ORACLE_ENOMEM;
+    }
+    for (int a = 0; a <= p; ++a)
+        for (int b = 0; b <= p - a; ++b)
+            for (int cc = 0; cc <= p - a - b; ++cc) {
+                const int64_t k = complete_index(p, a, b, cc);
+                ta[k] = a;
+                tb[k] = b;
+                tc[k] = cc;
+            }
     const double w = L / (double)K;
     for (int64_t c = 0; c < ncell; ++c) {
         double *Mc = M + c * cml;
@@ -535,22 +560,13 @@ int oracle_multipoles(int64_t n, const float *pos, double L, int32_t K, int32_t 
             const double X = (double)rel[4 * q + 0] * w;
             const double Y = (double)rel[4 * q + 1] * w;
             const double Z = (double)rel[4 * q + 2] * w;
-            int64_t k = 0;
-            double mx = 1.0;
-            for (int a = 0; a <= p; ++a) {
-                double mxy = mx;
-                for (int b = 0; b <= p - a; ++b) {
-                    double mxyz = mxy;
-                    for (int cc = 0; cc <= p - a - b; ++cc) {
-                        Mc[k++] += mxyz;
-                        mxyz *= Z;
-                    }
-                    mxy *= Y;
-                }
-                mx *= X;
-            }
+            for (int64_t k = 0; k < cml; ++k)
+                Mc[k] += int_power(X, ta[k]) * int_power(Y, tb[k]) * int_power(Z, tc[k]);
         }
     }
+    free(ta);
+    free(tb);
+    free(tc);
     if (!reduced) {
         memcpy(out, M, sizeof(double) * (size_t)(ncell * cml));
     } else {
@@ -583,7 +599,7 @@ int oracle_multipoles(int64_t n, const float *pos, double L, int32_t K, int32_t 
 }
 
 /* ------------------------------------------------------------------------- */
-/* Kick, drift and the time-step statistics (Sec. 2.1, Eq. 1).                 */
+/* Kick, drift and the time-step statistics (Sec. 3.1, Eq. 1).                 */
 /* ------------------------------------------------------------------------- */
 
 /* Periodic wrap of an FP64 coordinate into [0, L), rounded to FP32; a value

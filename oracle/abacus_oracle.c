@@ -17,6 +17,9 @@
  *                  image that lies in the neighbouring cell (Sec. 3.4.2), with
  *                  the spline-softened force of Eq. 3 and eps_s = 2.16 eps_p
  *                  (Sec. 3.2).
+ *   oracle_force_abs  per sink, the sum of the absolute summands of that
+ *                  acceleration and their number: the scale that bounds the
+ *                  rounding of any summation order.
  *   oracle_vjp     the vector-Jacobian product of those accelerations with a
  *                  cotangent, binning frozen (derived from Eq. 3).
  *   oracle_fd      a central finite difference of the same loss (binning
@@ -317,6 +320,51 @@ int oracle_forces(int64_t n, const float *pos, double L, int32_t K, int32_t R, d
         for (int a = 0; a < 3; ++a) acc[3 * k + a] = ctx.a[a];
     }
     if (npairs) *npairs = total;
+    grid_free(&g);
+    return ORACLE_OK;
+}
+
+typedef struct { law_t law; double s[3]; } abs_ctx;
+
+static void abs_pair(void *vctx, int64_t i, int64_t j, const double d[3])
+{
+    (void)i; (void)j;
+    abs_ctx *ctx = (abs_ctx *)vctx;
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (r == 0.0) return;
+    double f = law_f(&ctx->law, r);
+    for (int a = 0; a < 3; ++a) ctx->s[a] += fabs(f * d[a]);
+}
+
+/*
+ * oracle_force_abs: for the listed sinks (all if NULL), the sum over the near
+ * field of the absolute value of every summand of oracle_forces, per component,
+ *   abs_out[k][a] = sum_{j in NF(i)} |f(r_ij) d_ij,a|   (box units),
+ * and count_out[k] = the number of sources j summed (Sec. 3.4.1, Eq. 3).  Any
+ * summation order of the same terms in a floating-point format with unit
+ * roundoff u errs by at most about (count - 1) u abs_out (Higham's bound for
+ * recursive summation), so this is the scale the FP32 sums are checked against.
+ */
+int oracle_force_abs(int64_t n, const float *pos, double L, int32_t K, int32_t R, double eps_p,
+                     int32_t law, int64_t nsink, const int64_t *sinks, double *abs_out,
+                     int64_t *count_out)
+{
+    int rc = check_box(L, K, R, eps_p);
+    if (rc) return rc;
+    abs_ctx ctx;
+    if ((rc = make_law(law, eps_p, &ctx.law))) return rc;
+    if (n < 0 || nsink < 0 || (n > 0 && !pos) || (nsink > 0 && (!abs_out || !count_out)))
+        return ORACLE_EINVAL;
+    grid_t g;
+    rc = grid_build(&g, n, pos, L, K, NULL);
+    if (rc) return rc;
+    for (int64_t k = 0; k < nsink; ++k) {
+        int64_t i = sinks ? sinks[k] : k;
+        if (i < 0 || i >= n) { grid_free(&g); return ORACLE_EINVAL; }
+        ctx.s[0] = ctx.s[1] = ctx.s[2] = 0.0;
+        count_out[k] = visit_near_field(&g, pos, L, R, i, abs_pair, &ctx);
+        for (int a = 0; a < 3; ++a) abs_out[3 * k + a] = ctx.s[a];
+    }
     grid_free(&g);
     return ORACLE_OK;
 }

@@ -28,14 +28,19 @@ def cells(pos: np.ndarray, box: float, cpd: int) -> np.ndarray:
 
 
 def forces(pos: np.ndarray, box: float, cpd: int, radius: int, eps_plummer: float,
-           sinks=None, chunk: int = 256, law: str = "spline"):
-    """FP64 accelerations of ``sinks`` (all if None) and the ordered pair count."""
+           sinks=None, chunk: int = 256, law: str = "spline", absolute: bool = False):
+    """FP64 accelerations of ``sinks`` (all if None) and the ordered pair count.
+
+    With ``absolute`` the first result is instead, per sink and component, the
+    sum of the absolute summands sum_j |f d_ij,a| (f >= 0 for both laws), and
+    the second the per-sink number of near-field sources."""
     x = pos.astype(np.float64)
     n = x.shape[0]
     c = cells(pos, box, cpd)
     eps = 2.16 * eps_plummer
     idx = np.arange(n) if sinks is None else np.asarray(sinks, dtype=np.int64)
     out = np.zeros((idx.size, 3))
+    counts = np.zeros(idx.size, np.int64)
     npairs = 0
     for b in range(0, idx.size, chunk):
         ii = idx[b:b + chunk]
@@ -57,6 +62,10 @@ def forces(pos: np.ndarray, box: float, cpd: int, radius: int, eps_plummer: floa
         else:
             raise ValueError(law)
         f = np.where(near & (r > 0), f, 0.0)
-        out[b:b + ii.size] = np.einsum("ij,ijk->ik", f, d)
+        if absolute:
+            out[b:b + ii.size] = np.einsum("ij,ijk->ik", f, np.abs(d))
+            counts[b:b + ii.size] = near.sum(axis=1)
+        else:
+            out[b:b + ii.size] = np.einsum("ij,ijk->ik", f, d)
         npairs += int(near.sum())
-    return out, npairs
+    return (out, counts) if absolute else (out, npairs)

@@ -44,6 +44,7 @@ def _load():
     lib.oracle_bin.argtypes = [i64, vp, dbl, i32, vp, vp, vp, vp]
     lib.oracle_forces.argtypes = [i64, vp, dbl, i32, i32, dbl, i32, i64, vp, vp, vp]
     lib.oracle_vjp.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i32, i64, vp, vp]
+    lib.oracle_force_abs.argtypes = [i64, vp, dbl, i32, i32, dbl, i32, i64, vp, vp, vp]
     lib.oracle_fd.argtypes = [i64, vp, vp, dbl, i32, i32, dbl, i32, i64, i32, dbl, vp]
     lib.oracle_density.argtypes = [i64, vp, dbl, i32, i32, dbl, i64, vp, vp]
     lib.oracle_multipoles.argtypes = [i64, vp, dbl, i32, i32, i32, vp]
@@ -52,7 +53,7 @@ def _load():
     lib.oracle_kick_drift.argtypes = [i64, vp, vp, vp, dbl, i32, dbl, dbl, vp, vp, vp, vp]
     lib.oracle_timestep.argtypes = [vp, dbl, dbl, dbl, dbl]
     lib.oracle_timestep.restype = dbl
-    for f in ("oracle_bin", "oracle_forces", "oracle_vjp", "oracle_fd", "oracle_density",
+    for f in ("oracle_bin", "oracle_forces", "oracle_force_abs", "oracle_vjp", "oracle_fd", "oracle_density",
               "oracle_multipoles", "oracle_kick_drift"):
         getattr(lib, f).restype = ctypes.c_int
     lib.oracle_spline_over_plummer.restype = dbl
@@ -150,6 +151,24 @@ def forces(pos, box: float, cpd: int, radius: int, eps_plummer: float,
                                  _law(law), ns, _ptr(s), _ptr(acc), ctypes.byref(npairs)),
            "oracle_forces")
     return acc, int(npairs.value)
+
+
+def force_abs(pos, box: float, cpd: int, radius: int, eps_plummer: float,
+              sinks: Optional[np.ndarray] = None,
+              law: str = "spline") -> Tuple[np.ndarray, np.ndarray]:
+    """Per sink: sum_j |f(r_ij) d_ij,a| per component (box units) and the number
+    of near-field sources summed -- the scale that bounds the rounding of any
+    summation order of the sink's acceleration."""
+    p = _pos(pos)
+    n = p.shape[0]
+    s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+    ns = n if s is None else s.shape[0]
+    out = np.zeros((ns, 3), np.float64)
+    cnt = np.zeros(ns, np.int64)
+    _check(_load().oracle_force_abs(n, _ptr(p), float(box), int(cpd), int(radius),
+                                    float(eps_plummer), _law(law), ns, _ptr(s), _ptr(out),
+                                    _ptr(cnt)), "oracle_force_abs")
+    return out, cnt
 
 
 def vjp(pos, w, box: float, cpd: int, radius: int, eps_plummer: float,

@@ -291,6 +291,29 @@ def test_oracle_matches_brute_force(kind, n, cpd, seed):
     assert np.max(err) < 1e-10
 
 
+@pytest.mark.parametrize("kind,n,cpd,radius,seed", [("uniform", 1500, 7, 2, 21),
+                                                    ("clustered", 2000, 8, 2, 22),
+                                                    ("clustered", 1500, 9, 1, 23)])
+def test_force_abs_matches_brute_force(kind, n, cpd, radius, seed):
+    """The scale of the rounding bounds: sum_j |f d_ij,a| and the source count
+    per sink, against the numpy brute force; |a| <= that sum componentwise."""
+    pos = synth.uniform(n, seed) if kind == "uniform" else synth.clustered(n, 6, cpd, seed)
+    eps_p = 1.0 / (40 * n ** (1 / 3))
+    sinks = np.arange(0, n, 7)
+    s, cnt = oracle.force_abs(pos, 1.0, cpd, radius, eps_p, sinks)
+    ref, ref_cnt = brute.forces(pos, 1.0, cpd, radius, eps_p, sinks=sinks, absolute=True)
+    assert np.array_equal(cnt, ref_cnt)
+    assert np.max(np.abs(s - ref) / ref) < 1e-12
+    acc, npairs = oracle.forces(pos, 1.0, cpd, radius, eps_p, sinks)
+    assert npairs == int(cnt.sum())
+    assert np.all(np.abs(acc) <= s * (1 + 1e-12))
+    # Plummer law too
+    s, cnt = oracle.force_abs(pos, 1.0, cpd, radius, eps_p, sinks, law="plummer")
+    ref, _ = brute.forces(pos, 1.0, cpd, radius, eps_p, sinks=sinks, absolute=True,
+                          law="plummer")
+    assert np.max(np.abs(s - ref) / ref) < 1e-12
+
+
 def test_full_c1_matches_brute_force():
     b = synth.config("C1")[0]
     acc, npairs = oracle.forces(b.pos, b.box, b.cpd, b.radius, b.eps_plummer)

@@ -12,16 +12,23 @@ come from HIP events the library records around its kernels on the stream they
 run on.
 
 Workloads (``--workload``):
-  C2 (default)  clustered single box N = 128^3, K = 32.
+  C4 (default)  64 uneven clustered boxes, N_b log-uniform in [32^3, 128^3]:
+                the batched path (one persistent launch per kernel for all
+                boxes, autotuned, replayed from a HIP graph; ``value`` is the
+                graph replay), measured beside 64 sequential per-box calls with
+                the built-in shapes.
   C3            clustered single box N = 256^3, K = 64.
+  C2            clustered single box N = 128^3, K = 32.
   C5, C1        the small differentiation / uniform cases.
-  C4            64 uneven clustered boxes: the batched path (one persistent
-                launch per kernel for all boxes, autotuned, replayed from a HIP
-                graph; ``value`` is the graph replay) measured beside 64
-                sequential per-box calls with the built-in shapes.
 
-    python bench.py [--steps K] [--warmup W] [--workload C2|C3|C4|C5|C1]
+Beside the headline the line carries the error of the timed outputs against
+the FP64 oracle on sampled sinks (the same oracle calls, timed, give
+``cpu_baseline``), the single-box configurations C2 and C3 as ``configs``, and
+the widened rows (density, Plummer, FP64 kernel, multipoles, kick-drift) on C3.
+
+    python bench.py [--steps K] [--warmup W] [--workload C4|C3|C2|C5|C1]
                     [--accumulation compensated|chunked|single] [--no-cpu-baseline]
+                    [--no-configs] [--no-rows]
 """
 import argparse
 import hashlib
@@ -52,6 +59,8 @@ WORKLOADS = {
 # HBM traffic of the dominant kernel from rocprofv3 counter runs, kept beside
 # the profiles; used only while the kernel source is unchanged.
 TRAFFIC_FILES = {"C2": "profiles/hbm_traffic_clustered_N2M_K32.json"}
+# VALU instruction counters of the pair kernels, same rule.
+VALU_FILES = {}
 KERNEL_SOURCES = {"forward": "paper_2110_11392_amd/csrc/pairs.hip",
                   "adjoint": "paper_2110_11392_amd/csrc/vjp.hip"}
 
@@ -79,6 +88,35 @@ def traffic_bytes(workload, kernel):
     return kib * 1024.0
 
 
+def algorithmic_bytes(kernel, n, cells):
+    """The HBM bytes one launch of the pair kernel cannot avoid: every particle's
+    binned offsets (16 B) and permutation entry (4 B) read once, its result
+    (12 B) written once, the cotangent (12 B) read once by the adjoint, and one
+    4-byte cell offset per cell."""
+    per_particle = 16 + 4 + 12 + (12 if kernel == "adjoint" else 0)
+    return float(per_particle * n + 4 * cells)
+
+
+def valu_issue(workload, avg):
+    """Counter-derived VALU figures of the pair kernels (rocprofv3 SQ counters
+    kept beside the profiles), valid only while the kernel source is unchanged:
+    VALU instructions per pair, the useful-lane fraction and the issue rate in
+    VALU instructions per SIMD per 4 cycles (a wave64 instruction occupies a
+    16-lane SIMD for 4 cycles, so 1.0 is one instruction stream's full rate)."""
+    path = VALU_FILES.get(workload)
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    with open(os.path.join(ROOT, path)) as f:
+        rec = json.load(f)
+    out = {"source": path}
+    for kernel in ("forward", "adjoint"):
+        k = rec.get("kernels", {}).get(kernel)
+        if not k or k.get("source_sha256") != source_sha(kernel):
+            continue
+        out[kernel] = dict(k["derived"])
+    return out if len(out) > 1 else None
+
+
 def exact_pairs(cell_offsets, boxes):
     """sum_c n_c S_c - N from the cell offsets (S_c = particles in c's stencil)."""
     import numpy as np
@@ -98,33 +136,80 @@ def exact_pairs(cell_offsets, boxes):
     return total
 
 
-def cpu_baseline(boxes, budget_s=12.0):
-    """The FP64 oracle (single thread) on a bounded sample of sinks of the same
-    workload (for batches: of its largest box): forward forces plus the adjoint
-    for those sinks."""
+def host_cpu():
+    """The host CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return model, nproc
+
+
+def accuracy_sample(boxes, acc, grad, wvec, n_sinks, seed):
+    """The timed outputs against the FP64 oracle on ~n_sinks sinks drawn in
+    proportion to N_b: the forces' per-particle fractional error (median,
+    99.9th percentile) and the adjoint's relative 2-norm error with its
+    per-particle median / 99.9th percentile.  The oracle calls themselves
+    (single thread, forces + adjoint of those sinks) are timed and give the
+    CPU baseline in the metric's unit."""
     import numpy as np
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
     from paper_2110_11392_amd import synth
-    box = max(boxes, key=lambda b: b.n)
-    w = synth.gaussian_weights(box.n, 4242)
-    order = synth.sample_indices(box.n, min(box.n, 200000), 4243)
-    rng = np.random.default_rng(4244)
-    rng.shuffle(order)
-    pairs = 0
-    sinks_done = 0
-    t0 = time.perf_counter()
-    chunk = 500
-    while time.perf_counter() - t0 < budget_s and sinks_done < order.size:
-        s = np.sort(order[sinks_done:sinks_done + chunk])
-        _, npairs = oracle.forces(box.pos, box.box, box.cpd, box.radius, box.eps_plummer, s)
-        oracle.vjp(box.pos, w, box.box, box.cpd, box.radius, box.eps_plummer, s)
-        pairs += 2 * npairs
-        sinks_done += s.size
-    dt = time.perf_counter() - t0
-    return {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sinks_done} random sinks of the same workload (N={box.n}), FP64 forces "
-                      f"+ adjoint, {pairs} pair evaluations in {dt:.1f} s (single thread)"}
+    n_all = sum(b.n for b in boxes)
+    got_a, got_g, ref_a, ref_g = [], [], [], []
+    pairs, n_done, dt = 0, 0, 0.0
+    first = 0
+    for k, b in enumerate(boxes):
+        m = min(b.n, max(1, int(round(n_sinks * b.n / n_all)))) if b.n else 0
+        if m:
+            s = synth.sample_indices(b.n, m, seed + k)
+            wb = wvec[first:first + b.n]
+            t0 = time.perf_counter()
+            ra, npairs = oracle.forces(b.pos, b.box, b.cpd, b.radius, b.eps_plummer, s)
+            rg = oracle.vjp(b.pos, wb, b.box, b.cpd, b.radius, b.eps_plummer, s)
+            dt += time.perf_counter() - t0
+            pairs += 2 * npairs
+            n_done += s.size
+            ref_a.append(ra)
+            ref_g.append(rg)
+            got_a.append(acc[first + s].astype(np.float64))
+            got_g.append(grad[first + s].astype(np.float64))
+        first += b.n
+    a, ra = np.concatenate(got_a), np.concatenate(ref_a)
+    g, rg = np.concatenate(got_g), np.concatenate(ref_g)
+    nrm = np.linalg.norm(ra, axis=1)
+    keep = nrm > 0
+    e = np.linalg.norm(a[keep] - ra[keep], axis=1) / nrm[keep]
+    gn = np.linalg.norm(rg, axis=1)
+    gkeep = gn > 0
+    ge = np.linalg.norm(g[gkeep] - rg[gkeep], axis=1) / gn[gkeep]
+    accuracy = {
+        "sinks": int(n_done), "sampling": f"in proportion to N_b, seeds {seed}+b",
+        "force_frac_err_median": float(np.median(e)),
+        "force_frac_err_p999": float(np.percentile(e, 99.9)),
+        "adjoint_rel_err": float(np.linalg.norm(g - rg) / np.linalg.norm(rg)),
+        "adjoint_frac_err_median": float(np.median(ge)),
+        "adjoint_frac_err_p999": float(np.percentile(ge, 99.9)),
+        "tolerances": {"force_median": 1e-6, "force_p999": 1e-4, "adjoint_rel": 1e-4},
+    }
+    model, nproc = host_cpu()
+    baseline = {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
+                "sample": f"the accuracy sample: {n_done} sinks of the same workload drawn in "
+                          f"proportion to N_b, FP64 forces + adjoint of those sinks, {pairs} pair "
+                          f"evaluations in {dt:.1f} s on one thread (including the oracle's "
+                          f"binning of each sampled box)",
+                "cpu_model": model, "host_cores_available": nproc}
+    return accuracy, baseline
 
 
 class Stepper:
@@ -274,21 +359,63 @@ def timed(torch, fn, steps):
     return t0.elapsed_time(t1) / steps
 
 
+def run_config(anf, torch, name, accumulation, dev, steps, warmup, autotune, keep=False):
+    """One single-box configuration: tuned shapes, `steps` eager steps timed."""
+    from paper_2110_11392_amd import synth
+    log(f"[bench] config {name}: generating")
+    boxes = synth.config(name)
+    st = Stepper(anf, torch, boxes, accumulation, dev)
+    for _ in range(warmup):
+        st.step()
+    torch.cuda.synchronize()
+    st.binned.check_status()
+    tuning = None
+    if autotune:
+        tuning = st.nf.autotune(st.binned, accumulation)
+        st.step()
+        torch.cuda.synchronize()
+    pairs = exact_pairs(st.binned.cell_offsets.cpu().numpy(), boxes)
+    anf.timing_reset()
+    anf.timing_enable(True)
+    ms = timed(torch, st.step, steps)
+    anf.timing_enable(False)
+    avg = {k: (lambda r: r[0] / r[1] if r[1] else float("nan"))(anf.timing_read(i))
+           for k, i in (("forward", 0), ("adjoint", 1), ("bin", 2), ("plan", 3))}
+    rec = {"workload": f"{name}: {WORKLOADS[name]}", "n": st.nf.n_total,
+           "pairs_per_evaluation": pairs, "steps": steps, "ms_per_step": ms,
+           "value": 2.0 * pairs / (ms * 1e-3) / 1e9, "unit": "Gpairs/s", "timed": "eager calls",
+           "kernel_ms": avg, "tuning": tuning,
+           "forward_gpairs_per_s": pairs / (avg["forward"] * 1e-3) / 1e9,
+           "adjoint_gpairs_per_s": pairs / (avg["adjoint"] * 1e-3) / 1e9,
+           "forward_frac_fp32": FLOP_FWD * pairs / (avg["forward"] * 1e-3) / 1e12
+           / PEAK_FP32_TFLOPS,
+           "adjoint_frac_fp32": FLOP_ADJ * pairs / (avg["adjoint"] * 1e-3) / 1e12
+           / PEAK_FP32_TFLOPS,
+           "adjoint_over_forward": avg["adjoint"] / avg["forward"]}
+    return rec, (st, boxes) if keep else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--accumulation", default="compensated",
                     choices=["compensated", "chunked", "single"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle comparison of the timed outputs (and its timing)")
+    ap.add_argument("--accuracy-sinks", type=int, default=3000,
+                    help="sinks of the oracle comparison, drawn in proportion to N_b")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing candidates")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the measurement of the step replayed from a HIP graph")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single-box configurations C2 and C3 beside the headline")
+    ap.add_argument("--config-steps", type=int, default=5)
     ap.add_argument("--no-rows", action="store_true",
-                    help="skip the density / Plummer / multipole / kick-drift figures")
+                    help="skip the density / Plummer / FP64 / multipole / kick-drift figures")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -352,6 +479,10 @@ def main():
         graph = st.capture()
         graph_ms = timed(torch, graph.replay, args.steps)
         log(f"[bench] graph replay {graph_ms:.3f} ms/step")
+    # the outputs of the last timed step, compared with the oracle below
+    acc_out = st.acc.cpu().numpy()
+    grad_out = st.grad.cpu().numpy()
+    mom_out = st.mom.cpu().numpy()
 
     sequential_ms = None
     if args.workload == "C4":
@@ -371,9 +502,9 @@ def main():
         torch.cuda.synchronize()
         sequential_ms = timed(torch, sequential, args.steps)
         log(f"[bench] sequential {sequential_ms:.3f} ms/step")
+        del per_box
 
-    m = st.mom.cpu().numpy()
-    resid = float((np.abs(m[:, :3]).max(axis=1) / m[:, 3]).max())
+    resid = float((np.abs(mom_out[:, :3]).max(axis=1) / mom_out[:, 3]).max())
     fwd_tflops = FLOP_FWD * pairs / (avg["forward"] * 1e-3) / 1e12
     adj_tflops = FLOP_ADJ * pairs / (avg["adjoint"] * 1e-3) / 1e12
     dominant = "adjoint" if avg["adjoint"] >= avg["forward"] else "forward"
@@ -413,20 +544,39 @@ def main():
                      "traffic": tbytes,
                      "algorithmic_flop_per_launch": (FLOP_ADJ if dominant == "adjoint"
                                                      else FLOP_FWD) * pairs,
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(dominant, nf.n_total,
+                                                                       nf.cells_total),
                      "forward_tflops": fwd_tflops, "adjoint_tflops": adj_tflops,
-                     # the library is built without packed FP32, so one VALU
-                     # instruction per lane and cycle gives half the peak
-                     "frac_of_non_packed_fp32": achieved / (PEAK_FP32_TFLOPS / 2)},
+                     "valu": valu_issue(args.workload, avg)},
     }
-    if not args.no_rows:
-        log("[bench] widened rows: density, Plummer, multipoles, kick-drift")
-        out["rows"] = measure_rows(anf, torch, st, boxes, args.accumulation)
     if sequential_ms is not None:
         out["sequential_per_box_ms_per_step"] = sequential_ms
         out["batched_speedup_vs_sequential"] = sequential_ms / ms_value
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(boxes)
+        log(f"[bench] oracle comparison of the timed outputs on {args.accuracy_sinks} sinks")
+        accuracy, baseline = accuracy_sample(boxes, acc_out, grad_out,
+                                             st.wvec.cpu().numpy(), args.accuracy_sinks, 4250)
+        out["accuracy"] = accuracy
+        out["cpu_baseline"] = baseline
+        log(f"[bench] accuracy {accuracy}")
+    rows_src = (st, boxes)
+    if not args.no_configs:
+        out["configs"] = {}
+        for name in ("C2", "C3"):
+            if name == args.workload:
+                continue
+            rec, kept = run_config(anf, torch, name, args.accumulation, dev, args.config_steps,
+                                   2, not args.no_autotune, keep=(name == "C3"))
+            out["configs"][name] = rec
+            log(f"[bench] config {name}: {rec['value']:.1f} Gpairs/s")
+            if kept is not None:
+                rows_src = kept
+    if not args.no_rows:
+        rst, rboxes = rows_src
+        log(f"[bench] widened rows on {rboxes[0].n if len(rboxes) == 1 else 'the batch'}")
+        out["rows"] = measure_rows(anf, torch, rst, rboxes, args.accumulation)
+        out["rows"]["workload"] = ("C3: " + WORKLOADS["C3"]) if rst is not st else \
+            out["config"]["workload"]
     print(json.dumps(out), flush=True)
 
 

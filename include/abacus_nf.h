@@ -273,7 +273,7 @@ int abacus_nf_multipoles(const abacus_nf_box *boxes, int nboxes, const abacus_nf
                          int order, uint32_t flags, double *out, void *ws, size_t ws_bytes,
                          void *stream);
 
-/* ---- kick, drift and the time step (Sec. 2.1, Eq. 1) --------------------- */
+/* ---- kick, drift and the time step (Sec. 3.1, Eq. 1) --------------------- */
 
 /* Workspace bytes of abacus_nf_kick_drift (8 B x 2 per cell plus a little). */
 int abacus_nf_kick_drift_workspace_bytes(const abacus_nf_box *boxes, int nboxes,

@@ -1,4 +1,4 @@
-// Leapfrog kick and drift with the time-step statistics of Eq. 1 (Sec. 2.1).
+// Leapfrog kick and drift with the time-step statistics of Eq. 1 (Sec. 3.1).
 //
 // What it computes, per particle (FP32 state; each update formed in FP64 with
 // separate multiply and add, rounded once to FP32):

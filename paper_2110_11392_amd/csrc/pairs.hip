@@ -179,8 +179,9 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ src3, int 
 // reads its own run's records from there: two distinct LDS addresses per read,
 // served as broadcasts.  (Per-lane global loads of the same records took the
 // L1 address path for 16 cycles per record and wave.)  Lanes of the shorter
-// run stop at its end; the sums are folded per chunk like a cell's (the single
-// and chunked modes add the chunk's sum to the running accumulator).
+// run stop at its end.  The single mode keeps adding every pair to the one
+// running accumulator; the chunked and compensated modes fold each chunk's sum
+// into it like a cell's.
 template <int kAcc, int kU>
 __device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3,
                                               float* __restrict__ slot, int lane, bool upper,
@@ -190,19 +191,23 @@ __device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3,
   const int nmax = nl > nh ? nl : nh;
   const int rn = upper ? nh : nl;
   const float* mine = slot + (upper ? 3 * kChunk : 0);
+  const float* __restrict__ runl = src3 + 3 * (int64_t)bl;
+  const float* __restrict__ runh = src3 + 3 * (int64_t)bh;
   for (int cb = 0; cb < nmax; cb += kChunk) {
     const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
     if (cb + lane < nl) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) slot[3 * lane + c] = src3[3 * (bl + cb + lane) + c];
+      for (int c = 0; c < 3; ++c) slot[3 * lane + c] = runl[3 * (cb + lane) + c];
     }
     if (cb + lane < nh) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) slot[3 * kChunk + 3 * lane + c] = src3[3 * (bh + cb + lane) + c];
+      for (int c = 0; c < 3; ++c) slot[3 * kChunk + 3 * lane + c] = runh[3 * (cb + lane) + c];
     }
     __builtin_amdgcn_wave_barrier();
     const int n = (rn < ce ? rn : ce) - cb;  // this lane's positions in the chunk
-    float tx = 0.f, ty = 0.f, tz = 0.f, rho = 0.f;
+    // SINGLE: the running accumulator itself; otherwise a fresh chunk partial
+    const bool one = kAcc == kAccSingle;
+    float tx = one ? ax : 0.f, ty = one ? ay : 0.f, tz = one ? az : 0.f, rho = 0.f;
     int j = 0;
     for (; j + kU <= n; j += kU) {
       float c[3 * kU];
@@ -214,8 +219,10 @@ __device__ __forceinline__ void sum_edge_runs(const float* __restrict__ src3,
       interact<false, false>(mine[3 * j], mine[3 * j + 1], mine[3 * j + 2], qx, qy, qz, k, tx, ty,
                              tz, rho);
     __builtin_amdgcn_wave_barrier();
-    if (n > 0) {
-      if (kAcc == kAccSingle || kAcc == kAccChunked) {
+    if (kAcc == kAccSingle) {
+      ax = tx; ay = ty; az = tz;
+    } else if (n > 0) {
+      if (kAcc == kAccChunked) {
         ax += tx; ay += ty; az += tz;
       } else {
         two_sum_fold(ax, ex, tx);
@@ -345,21 +352,21 @@ __attribute__((amdgpu_waves_per_eu(fwd_min_waves<kU, kCount, kDens>(), 8))) void
             if (kCount) npairs += end - beg;
             if (kAcc == kAccSingle) {
               if (near)
-                sum_sources<kU, kPipe, true, kDens>(src3, beg, end, qx, qy, qz, kc, ax, ay, az, rho);
+                sum_sources<kU, kPipe, true, kDens>(src3 + 3 * (int64_t)beg, 0, end - beg, qx, qy, qz, kc, ax, ay, az, rho);
               else if (dens_here)
-                sum_sources<kU, kPipe, false, kDens>(src3, beg, end, qx, qy, qz, kc, ax, ay, az, rho);
+                sum_sources<kU, kPipe, false, kDens>(src3 + 3 * (int64_t)beg, 0, end - beg, qx, qy, qz, kc, ax, ay, az, rho);
               else
-                sum_sources<kU, kPipe, false, false>(src3, beg, end, qx, qy, qz, kc, ax, ay, az, rho);
+                sum_sources<kU, kPipe, false, false>(src3 + 3 * (int64_t)beg, 0, end - beg, qx, qy, qz, kc, ax, ay, az, rho);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
                 if (near)
-                  sum_sources<kU, kPipe, true, kDens>(src3, cb, ce, qx, qy, qz, kc, tx, ty, tz, rho);
+                  sum_sources<kU, kPipe, true, kDens>(src3 + 3 * (int64_t)cb, 0, ce - cb, qx, qy, qz, kc, tx, ty, tz, rho);
                 else if (dens_here)
-                  sum_sources<kU, kPipe, false, kDens>(src3, cb, ce, qx, qy, qz, kc, tx, ty, tz, rho);
+                  sum_sources<kU, kPipe, false, kDens>(src3 + 3 * (int64_t)cb, 0, ce - cb, qx, qy, qz, kc, tx, ty, tz, rho);
                 else
-                  sum_sources<kU, kPipe, false, false>(src3, cb, ce, qx, qy, qz, kc, tx, ty, tz, rho);
+                  sum_sources<kU, kPipe, false, false>(src3 + 3 * (int64_t)cb, 0, ce - cb, qx, qy, qz, kc, tx, ty, tz, rho);
                 if (kAcc == kAccChunked) {
                   ax += tx; ay += ty; az += tz;
                 } else {

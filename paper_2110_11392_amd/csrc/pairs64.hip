@@ -87,15 +87,17 @@ __device__ __forceinline__ void sum64_edge_runs(const float* __restrict__ src3,
   const int nmax = nl > nh ? nl : nh;
   const int rn = upper ? nh : nl;
   const float* mine = slot + (upper ? 3 * kChunk : 0);
+  const float* __restrict__ runl = src3 + 3 * (int64_t)bl;
+  const float* __restrict__ runh = src3 + 3 * (int64_t)bh;
   for (int cb = 0; cb < nmax; cb += kChunk) {
     const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
     if (cb + lane < nl) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) slot[3 * lane + c] = src3[3 * (bl + cb + lane) + c];
+      for (int c = 0; c < 3; ++c) slot[3 * lane + c] = runl[3 * (cb + lane) + c];
     }
     if (cb + lane < nh) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) slot[3 * kChunk + 3 * lane + c] = src3[3 * (bh + cb + lane) + c];
+      for (int c = 0; c < 3; ++c) slot[3 * kChunk + 3 * lane + c] = runh[3 * (cb + lane) + c];
     }
     __builtin_amdgcn_wave_barrier();
     const int n = (rn < ce ? rn : ce) - cb;
@@ -175,9 +177,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
           if (active && oz >= -R && oz <= R) {
             const double qz = (double)p.z - (double)oz;
             if (near)
-              sum64<true>(src3, beg, end, qx, qy, qz, kc, ax, ay, az);
+              sum64<true>(src3 + 3 * (int64_t)beg, 0, end - beg, qx, qy, qz, kc, ax, ay, az);
             else
-              sum64<false>(src3, beg, end, qx, qy, qz, kc, ax, ay, az);
+              sum64<false>(src3 + 3 * (int64_t)beg, 0, end - beg, qx, qy, qz, kc, ax, ay, az);
           }
         }
         if (pair_edges) {

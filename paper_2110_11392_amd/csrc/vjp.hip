@@ -189,8 +189,9 @@ __device__ __forceinline__ void sum_adjoint(const float* __restrict__ src6, int 
 // reads its own run's records from there: two distinct LDS addresses per read,
 // served as broadcasts.  (Per-lane global loads of the same records took the
 // L1 address path for 24 cycles per record and wave.)  Lanes of the shorter
-// run stop at its end; the sums are folded per chunk like a cell's (the single
-// and chunked modes add the chunk's sum to the running accumulator).
+// run stop at its end.  The single mode keeps adding every pair to the one
+// running accumulator; the chunked and compensated modes fold each chunk's sum
+// into it like a cell's.
 constexpr int kEdgeRec = 6;
 
 template <int kAcc>
@@ -204,20 +205,24 @@ __device__ __forceinline__ void adjoint_edge_runs(const float* __restrict__ src6
   const int nmax = nl > nh ? nl : nh;
   const int rn = upper ? nh : nl;
   const float* mine = slot + (upper ? kChunk * kEdgeRec : 0);
+  const float* __restrict__ runl = src6 + kEdgeRec * (int64_t)bl;
+  const float* __restrict__ runh = src6 + kEdgeRec * (int64_t)bh;
   for (int cb = 0; cb < nmax; cb += kChunk) {
     const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
     if (cb + lane < nl) {
 #pragma unroll
-      for (int c = 0; c < kEdgeRec; ++c) slot[kEdgeRec * lane + c] = src6[kEdgeRec * (bl + cb + lane) + c];
+      for (int c = 0; c < kEdgeRec; ++c) slot[kEdgeRec * lane + c] = runl[kEdgeRec * (cb + lane) + c];
     }
     if (cb + lane < nh) {
 #pragma unroll
       for (int c = 0; c < kEdgeRec; ++c)
-        slot[kChunk * kEdgeRec + kEdgeRec * lane + c] = src6[kEdgeRec * (bh + cb + lane) + c];
+        slot[kChunk * kEdgeRec + kEdgeRec * lane + c] = runh[kEdgeRec * (cb + lane) + c];
     }
     __builtin_amdgcn_wave_barrier();
     const int n = (rn < ce ? rn : ce) - cb;  // this lane's positions in the chunk
-    float tx = 0.f, ty = 0.f, tz = 0.f;
+    // SINGLE: the running accumulator itself; otherwise a fresh chunk partial
+    const bool one = kAcc == kAccSingle;
+    float tx = one ? gx : 0.f, ty = one ? gy : 0.f, tz = one ? gz : 0.f;
     int j = 0;
     for (; j + 2 <= n; j += 2) {
       float c2[2 * kEdgeRec];
@@ -236,8 +241,10 @@ __device__ __forceinline__ void adjoint_edge_runs(const float* __restrict__ src6
                      ty, tz);
     }
     __builtin_amdgcn_wave_barrier();
-    if (n > 0) {
-      if (kAcc == kAccSingle || kAcc == kAccChunked) {
+    if (kAcc == kAccSingle) {
+      gx = tx; gy = ty; gz = tz;
+    } else if (n > 0) {
+      if (kAcc == kAccChunked) {
         gx += tx; gy += ty; gz += tz;
       } else {
         two_sum_fold(gx, ex, tx);
@@ -330,12 +337,13 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
     const bool upper = lane_z == zb;
     float px = 0.f, py = 0.f, pz = 0.f, wkx = 0.f, wky = 0.f, wkz = 0.f;
     if (active) {
-      px = src6[6 * s + 0];
-      py = src6[6 * s + 1];
-      pz = src6[6 * s + 2];
-      wkx = src6[6 * s + 3];
-      wky = src6[6 * s + 4];
-      wkz = src6[6 * s + 5];
+      const float* __restrict__ mine = src6 + 6 * (int64_t)s;
+      px = mine[0];
+      py = mine[1];
+      pz = mine[2];
+      wkx = mine[3];
+      wky = mine[4];
+      wkz = mine[5];
     }
 
     // (G, E): the sink's sum; (g, e): the current x-offset slice (SINGLE keeps
@@ -365,20 +373,20 @@ __attribute__((amdgpu_waves_per_eu(vjp_min_waves<kU>(), 8))) void k_pair_vjp(
             const float qz = pz - (float)oz;
             if (kAcc == kAccSingle) {
               if (near)
-                sum_adjoint<kU, kPipe, true>(src6, beg, end, qx, qy, qz, wkx, wky, wkz, kc, gx,
+                sum_adjoint<kU, kPipe, true>(src6 + 6 * (int64_t)beg, 0, end - beg, qx, qy, qz, wkx, wky, wkz, kc, gx,
                                              gy, gz);
               else
-                sum_adjoint<kU, kPipe, false>(src6, beg, end, qx, qy, qz, wkx, wky, wkz, kc, gx,
+                sum_adjoint<kU, kPipe, false>(src6 + 6 * (int64_t)beg, 0, end - beg, qx, qy, qz, wkx, wky, wkz, kc, gx,
                                               gy, gz);
             } else {
               for (int cb = beg; cb < end; cb += kChunk) {
                 const int ce = cb + kChunk < end ? cb + kChunk : end;
                 float tx = 0.f, ty = 0.f, tz = 0.f;
                 if (near)
-                  sum_adjoint<kU, kPipe, true>(src6, cb, ce, qx, qy, qz, wkx, wky, wkz, kc, tx,
+                  sum_adjoint<kU, kPipe, true>(src6 + 6 * (int64_t)cb, 0, ce - cb, qx, qy, qz, wkx, wky, wkz, kc, tx,
                                                ty, tz);
                 else
-                  sum_adjoint<kU, kPipe, false>(src6, cb, ce, qx, qy, qz, wkx, wky, wkz, kc, tx,
+                  sum_adjoint<kU, kPipe, false>(src6 + 6 * (int64_t)cb, 0, ce - cb, qx, qy, qz, wkx, wky, wkz, kc, tx,
                                                 ty, tz);
                 if (kAcc == kAccChunked) {
                   gx += tx; gy += ty; gz += tz;

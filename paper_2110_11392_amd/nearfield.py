@@ -309,13 +309,21 @@ class _NearFieldFn(torch.autograd.Function):
 
 
 def near_field(pos: torch.Tensor, box: float, cpd: int, radius: int, eps_plummer: float,
-               compensated: bool = True, nf: Optional[NearField] = None,
+               accumulation: str = "compensated", nf: Optional[NearField] = None,
                law: str = "spline") -> torch.Tensor:
-    """Near-field accelerations of one periodic box, differentiable in ``pos``."""
+    """Near-field accelerations of one periodic box, differentiable in ``pos``.
+
+    ``accumulation`` is how each sink's FP32 sum is formed, in the forward and
+    the adjoint alike: "single" (one running FP32 accumulator, as the paper's
+    kernel), "chunked" (FP32 partials over at most 64 sources added to it) or
+    "compensated" (those partials folded into an FP32 sum and error term)."""
+    if accumulation not in ACCUMULATION:
+        raise ValueError(f"unknown accumulation {accumulation!r}; "
+                         f"one of {sorted(ACCUMULATION)}")
     if nf is None:
         nf = NearField([BoxSpec(pos.shape[0], box, cpd, radius, eps_plummer)], device=pos.device,
                        law=law)
-    return _NearFieldFn.apply(pos, nf, "compensated" if compensated else "chunked")
+    return _NearFieldFn.apply(pos, nf, accumulation)
 
 
 def timestep(box_stats, a: float, H: float, eta_acc: float, eta_H: float) -> float:

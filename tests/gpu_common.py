@@ -54,3 +54,40 @@ def pair_count(boxes):
                     s += np.roll(n, (ox, oy, oz), axis=(0, 1, 2))
         total += int((n * s).sum()) - b.n
     return total
+
+
+# Unit roundoff of FP32.
+U32 = 2.0 ** -24
+
+
+def single_sum_bound_violations(single, comp, ref, s_abs, count):
+    """Number of (sink, component) entries where the single-accumulator result
+    departs from the oracle by more than the compensated result does plus the
+    rounding one FP32 running sum allows.
+
+    Both modes add the same computed pair terms t (each an exact product folded
+    in by one fused multiply-add), so
+      |single - sum t| <= (n - 1) u sum|t|      (one running sum of n terms),
+      |comp - sum t|   <= (63 + 5) u sum|t|     (sums of <= 64 terms, folded
+                                                 with TwoSum, a few roundings),
+    to first order in u = 2^-24, with n = count + 1 (the sink's own zero term).
+    sum|t| is taken as twice the oracle's sum of absolute summands ``s_abs``,
+    which covers the FP32 terms' own relative error.  Hence
+      |single - ref| <= |comp - ref| + 2 (count + 1 + 68) u s_abs."""
+    single = np.asarray(single, np.float64)
+    comp = np.asarray(comp, np.float64)
+    lim = np.abs(comp - ref) + 2.0 * (np.asarray(count)[:, None] + 69) * U32 * s_abs
+    return int((np.abs(single - ref) > lim).sum())
+
+
+def oracle_abs_boxes(boxes):
+    """oracle.force_abs of every particle of a box list, concatenated (empty
+    boxes contribute nothing), matching oracle_forces_boxes' order."""
+    s, c = [], []
+    for b in boxes:
+        if b.n == 0:
+            continue
+        sb, cb = oracle.force_abs(b.pos, b.box, b.cpd, b.radius, b.eps_plummer)
+        s.append(sb)
+        c.append(cb)
+    return np.concatenate(s), np.concatenate(c)

@@ -111,3 +111,26 @@ def test_kdk_c2_deterministic_and_timestep(anf):
     bs = got[3][0]
     assert anf.timestep(bs, 0.5, 1.2, 0.25, 0.03) == pytest.approx(
         oracle.timestep(bs, 0.5, 1.2, 0.25, 0.03), rel=1e-15)
+
+
+def test_kdk_cells_cut_by_tiles(anf):
+    """Crowded cells spanning several 1024-slot tiles of the update (their
+    statistics are added from per-tile pieces), a cell that fills whole tiles,
+    and particles stored in cell order (contiguous gathers)."""
+    crowd = (np.array([0.3, 0.6, 0.55], np.float32) +
+             np.float32(0.01) * (synth.uniform(5000, 41) - np.float32(0.5))).astype(np.float32)
+    pos = np.concatenate([synth.uniform(3000, 40), crowd,
+                          (np.array([0.9, 0.1, 0.1], np.float32) + np.float32(0.005) *
+                           synth.uniform(1500, 42)).astype(np.float32)])
+    say("[kdk] crowded cells across tiles")
+    run_case(anf, [synth.Box(pos, 1.0, 8, 2, 1 / 800)], 0.02, 0.01)
+    # one cell holds every particle of the box: every tile boundary cuts it
+    one = (np.float32(0.5) + np.float32(0.01) * synth.uniform(4500, 43)).astype(np.float32)
+    say("[kdk] a single occupied cell")
+    run_case(anf, [synth.Box(one, 1.0, 5, 2, 1 / 500)], -0.01, 0.03)
+    # cell order: sort the particles by the oracle's binning first
+    b = synth.config("C1")[0]
+    _, _, perm, _ = oracle.bin(b.pos, b.box, b.cpd)
+    say("[kdk] C1 in cell order")
+    run_case(anf, [synth.Box(np.ascontiguousarray(b.pos[perm]), b.box, b.cpd, b.radius,
+                             b.eps_plummer)], 0.01, 0.02)

@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import (MEDIAN_TOL, P999_TOL, VJP_TOL, err_stats, frac_err, oracle_bin_boxes,
-                        pair_count)
+from gpu_common import (MEDIAN_TOL, P999_TOL, VJP_TOL, err_stats, frac_err, oracle_abs_boxes,
+                        oracle_bin_boxes, pair_count, single_sum_bound_violations)
 from paper_2110_11392_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -172,9 +172,10 @@ def oracle_forces_boxes(boxes, sinks_per_box=None):
 @pytest.mark.parametrize("name", list(small_boxes().keys()))
 @pytest.mark.parametrize("accumulation", ["compensated", "chunked", "single"])
 def test_forces_small_full(nfmod, name, accumulation):
+    anf = nfmod
     boxes = small_boxes()[name]
     say(f"[forces] {name} {accumulation}")
-    acc, _, pairs = gpu_forces(nfmod, boxes, accumulation, count_pairs=True)
+    acc, _, pairs = gpu_forces(anf, boxes, accumulation, count_pairs=True)
     assert pairs == pair_count(boxes)
     ref, idx = oracle_forces_boxes(boxes)
     e = frac_err(acc[idx], ref)
@@ -183,6 +184,12 @@ def test_forces_small_full(nfmod, name, accumulation):
     assert np.all(np.isfinite(acc))
     if accumulation != "single":
         assert st["median"] <= MEDIAN_TOL and st["p999"] <= P999_TOL
+    else:
+        # one FP32 running sum per sink: within the recursive-summation bound
+        # of the compensated result (derivation in gpu_common)
+        comp, _, _ = gpu_forces(anf, boxes, "compensated")
+        s_abs, cnt = oracle_abs_boxes(boxes)
+        assert single_sum_bound_violations(acc[idx], comp[idx], ref, s_abs, cnt) == 0
 
 
 @pytest.mark.parametrize("name", ["C5", "C2", "C3"])
@@ -342,12 +349,20 @@ def test_vjp_pairs_inside_softening(nfmod, name):
     assert np.median(per) <= 1e-5
 
 
-def test_autograd_matches_vjp(nfmod):
+@pytest.mark.parametrize("accumulation", ["compensated", "chunked", "single"])
+def test_autograd_matches_vjp(nfmod, accumulation):
     b = synth.config("C1")[0]
     pos = torch.from_numpy(b.pos).cuda().requires_grad_(True)
-    acc = nfmod.near_field(pos, b.box, b.cpd, b.radius, b.eps_plummer)
+    acc = nfmod.near_field(pos, b.box, b.cpd, b.radius, b.eps_plummer, accumulation)
     w = torch.from_numpy(synth.gaussian_weights(b.n, 5)).cuda()
     (acc * w).sum().backward()
+    # the autograd form is the library's forward and adjoint in that mode
+    nf = make_nf(nfmod, [b])
+    bd = nf.bin(torch.from_numpy(b.pos).cuda())
+    direct, _, _ = nf.forces(bd, accumulation)
+    assert torch.equal(acc.detach(), direct)
     ref = oracle.vjp(b.pos, w.cpu().numpy(), b.box, b.cpd, b.radius, b.eps_plummer)
     g = pos.grad.cpu().numpy()
     assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= VJP_TOL
+    with pytest.raises(ValueError):
+        nfmod.near_field(pos, b.box, b.cpd, b.radius, b.eps_plummer, "kahan")

@@ -1,4 +1,4 @@
-"""Pins of the kick-drift oracle and the Eq. 1 time step (Sec. 2.1).
+"""Pins of the kick-drift oracle and the Eq. 1 time step (Sec. 3.1).
 
   * a uniform acceleration is integrated exactly by kick-drift-kick leapfrog:
     after n steps x = x0 + v0 t + a t^2 / 2 and v = v0 + a t (to FP32 rounding);

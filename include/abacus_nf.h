@@ -46,6 +46,7 @@ extern "C" {
 #define ABACUS_NF_ERANGE     (-2)  /* sizes beyond the int32 index space of the kernels */
 #define ABACUS_NF_EWORKSPACE (-3)  /* workspace missing, misaligned or too small */
 #define ABACUS_NF_EHIP       (-4)  /* a HIP runtime call failed; see abacus_nf_strerror */
+#define ABACUS_NF_ESCRATCH   (-5)  /* too large for abacus_nf_forces_noalloc's static scratch */
 
 /* ---- device status bits (int32 written by abacus_nf_bin) ---------------- */
 #define ABACUS_NF_STATUS_BADPOS 0x1  /* a coordinate was non-finite or |x K / L| >= 2^30 */
@@ -160,6 +161,27 @@ int abacus_nf_bin(const abacus_nf_box *boxes, int nboxes, const float *pos,
 int abacus_nf_forces(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
                      float *acc, float *density, double *momentum, int64_t *pair_count,
                      uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * abacus_nf_forces_noalloc -- abacus_nf_forces for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments without the workspace,
+ * the same kernels and the same results bit for bit.
+ *   Temporaries live in a static 64 MiB device array of the library (one per
+ *   GPU, held until the process ends); its address is looked up once per
+ *   device, on the first call with that device current.  `stream` must belong
+ *   to the current device.  Nothing is allocated or freed.
+ *   Limit: the work plan, the packed 12-byte source records and the momentum
+ *   partials must fit the 64 MiB -- about 4 M particles at 64 per cell --
+ *   else ABACUS_NF_ESCRATCH is returned before anything is enqueued.
+ *   Every call on one GPU uses that GPU's one array, and the array keeps the
+ *   last call's contents (each call clears what it needs cleared): calls that
+ *   overlap in time on one GPU (different streams, different threads) race and
+ *   must be ordered by the caller.
+ */
+int abacus_nf_forces_noalloc(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                             float *acc, float *density, double *momentum,
+                             int64_t *pair_count, uint32_t flags, void *stream);
 
 /*
  * abacus_nf_forces_f64 -- the same near-field accelerations with every

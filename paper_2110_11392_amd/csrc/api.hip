@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -140,6 +141,10 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = f
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Tail items split per launch of abacus_nf_forces_noalloc (their slice
+// partials take 9 MB of its scratch at 2R + 1 = 5 slices).
+constexpr int64_t kNoAllocMaxSplit = 1024;
+
 struct Layout {
   // shared
   size_t boxtab;
@@ -153,7 +158,10 @@ struct Layout {
   int64_t max_items, max_tasks, max_split;
 };
 
-Layout layout(const Resolved& r) {
+// Workspace layout.  `forward_only` lays out just what abacus_nf_forces needs
+// (no binning region, 12-byte source records) for the static scratch of
+// abacus_nf_forces_noalloc.
+Layout layout(const Resolved& r, bool forward_only = false) {
   Layout L;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
@@ -164,15 +172,18 @@ Layout layout(const Resolved& r) {
   L.boxtab = take(sizeof(DevBox) * r.boxes.size());
   const size_t region = o;
   const int64_t n = r.n_total, c = r.cells_total;
-  const int64_t rb = radix_blocks(n);
-  L.keys0 = take(4 * (size_t)n);
-  L.keys1 = take(4 * (size_t)n);
-  L.vals0 = take(4 * (size_t)n);
-  L.vals1 = take(4 * (size_t)n);
-  L.hist = take(4 * (size_t)(256 * rb));
-  L.hist_scan = take(4 * (size_t)(256 * rb + 1));
-  int64_t scan_n = c > 256 * rb ? c : 256 * rb;
-  L.bin_scan = take(4 * (size_t)scan_tmp_ints(scan_n));
+  L.keys0 = L.keys1 = L.vals0 = L.vals1 = L.hist = L.hist_scan = L.bin_scan = 0;
+  if (!forward_only) {
+    const int64_t rb = radix_blocks(n);
+    L.keys0 = take(4 * (size_t)n);
+    L.keys1 = take(4 * (size_t)n);
+    L.vals0 = take(4 * (size_t)n);
+    L.vals1 = take(4 * (size_t)n);
+    L.hist = take(4 * (size_t)(256 * rb));
+    L.hist_scan = take(4 * (size_t)(256 * rb + 1));
+    int64_t scan_n = c > 256 * rb ? c : 256 * rb;
+    L.bin_scan = take(4 * (size_t)scan_tmp_ints(scan_n));
+  }
   const size_t bin_end = o;
   o = region;
   L.max_items = plan_max_items(n, c, r.pencils_total);
@@ -182,14 +193,19 @@ Layout layout(const Resolved& r) {
   L.item_bucket = take(4 * (size_t)L.max_items);
   L.item_slot = take(4 * (size_t)L.max_items);
   L.item_cost = take(4 * (size_t)L.max_items);
-  L.max_split = r.split_slices > 1 ? std::min<int64_t>(kMaxSplit, L.max_items) : 0;
+  // (the forward-only layout keeps room for fewer split tail items: splitting
+  // changes which task sums a slice, never the result)
+  L.max_split = r.split_slices > 1
+                    ? std::min<int64_t>(forward_only ? kNoAllocMaxSplit : kMaxSplit, L.max_items)
+                    : 0;
   L.max_tasks = plan_max_tasks(L.max_items, L.max_split);
   L.tasks = take(4 * (size_t)L.max_tasks);
   L.ctrl = take(4 * (size_t)kCtrlInts);
   L.partial = take(sizeof(float) * kPartialStride * kTile * (size_t)(L.max_split * r.split_slices));
   L.plan_scan = take(4 * (size_t)scan_tmp_ints(r.pencils_total));
   L.mom = take(sizeof(double) * 4 * kMomChunks * r.boxes.size());
-  L.src_w = take(6 * sizeof(float) * (size_t)n);  // packed source records
+  // packed source records: 6 floats for the adjoint, 3 for the forward kernel
+  L.src_w = take((forward_only ? 3 : 6) * sizeof(float) * (size_t)n);
   const size_t force_end = o;
   L.total = bin_end > force_end ? bin_end : force_end;
   return L;
@@ -321,6 +337,48 @@ bool binned_ok(const abacus_nf_binned* b, int64_t n_total) {
   return b && b->cell_offsets && b->status && (n_total == 0 || (b->perm && b->rel));
 }
 
+int forces_args(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                const float* acc, const float* density, const int64_t* pair_count,
+                uint32_t flags, Resolved* r, AccMode* mode);
+int forces_launch(const abacus_nf_box* boxes, int nboxes, const Resolved& r, AccMode mode,
+                  bool count, const abacus_nf_binned* b, float* acc, float* density,
+                  double* momentum, int64_t* pair_count, void* ws, const Layout& L,
+                  hipStream_t s);
+
+// ---- the static scratch of abacus_nf_forces_noalloc -----------------------
+// Every GPU the library runs on holds its own copy of this array until the
+// process ends.  Host code never uses the array's name as an address (on the
+// host it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// that pointer is what the kernels receive.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> device address of `scratch`
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  const auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return ABACUS_NF_OK;
+  }
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!p || (reinterpret_cast<uintptr_t>(p) & 255u) != 0) {
+    g_last_hip_error = "hipGetSymbolAddress(scratch): null or misaligned address";
+    return ABACUS_NF_EHIP;
+  }
+  g_scratch_ptr[dev] = p;
+  *out = p;
+  return ABACUS_NF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -373,16 +431,53 @@ int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_bin
                      float* acc, float* density, double* momentum, int64_t* pair_count,
                      uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
   Resolved r;
-  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
-  if (rc) return rc;
   AccMode mode;
-  if ((rc = acc_mode(flags, &mode))) return rc;
-  const bool count = (flags & ABACUS_NF_COUNT_PAIRS) != 0;
-  if (!binned_ok(b, r.n_total) || (r.n_total > 0 && !acc) || (count && !pair_count)) return ABACUS_NF_EINVAL;
-  if (density && (count || !r.density_ok)) return ABACUS_NF_EINVAL;
+  int rc = forces_args(boxes, nboxes, b, acc, density, pair_count, flags, &r, &mode);
+  if (rc) return rc;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  return forces_launch(boxes, nboxes, r, mode, (flags & ABACUS_NF_COUNT_PAIRS) != 0, b, acc,
+                       density, momentum, pair_count, ws, L, static_cast<hipStream_t>(stream));
+}
+
+int abacus_nf_forces_noalloc(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                             float* acc, float* density, double* momentum, int64_t* pair_count,
+                             uint32_t flags, void* stream) {
+  Resolved r;
+  AccMode mode;
+  int rc = forces_args(boxes, nboxes, b, acc, density, pair_count, flags, &r, &mode);
+  if (rc) return rc;
+  const Layout L = layout(r, true);
+  if (L.total > kNoAllocScratchBytes) return ABACUS_NF_ESCRATCH;
+  void* ws = nullptr;
+  if ((rc = noalloc_scratch(&ws))) return rc;
+  return forces_launch(boxes, nboxes, r, mode, (flags & ABACUS_NF_COUNT_PAIRS) != 0, b, acc,
+                       density, momentum, pair_count, ws, L, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+int forces_args(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                const float* acc, const float* density, const int64_t* pair_count,
+                uint32_t flags, Resolved* r, AccMode* mode) {
+  int rc = resolve(boxes, nboxes, r, (flags & ABACUS_NF_PLUMMER) != 0);
+  if (rc) return rc;
+  if ((rc = acc_mode(flags, mode))) return rc;
+  const bool count = (flags & ABACUS_NF_COUNT_PAIRS) != 0;
+  if (!binned_ok(b, r->n_total) || (r->n_total > 0 && !acc) || (count && !pair_count))
+    return ABACUS_NF_EINVAL;
+  if (density && (count || !r->density_ok)) return ABACUS_NF_EINVAL;
+  return ABACUS_NF_OK;
+}
+
+// Plan, forward pair kernel and momentum reduction of one abacus_nf_forces
+// call, with every temporary in `ws` laid out as L.
+int forces_launch(const abacus_nf_box* boxes, int nboxes, const Resolved& r, AccMode mode,
+                  bool count, const abacus_nf_binned* b, float* acc, float* density,
+                  double* momentum, int64_t* pair_count, void* ws, const Layout& L,
+                  hipStream_t s) {
   DevBox* dboxes = at<DevBox>(ws, L.boxtab);
   ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
   if (count) ANF_HIP(fill_i64(pair_count, 0, 1, s), "pair counter");
@@ -409,6 +504,10 @@ int abacus_nf_forces(const abacus_nf_box* boxes, int nboxes, const abacus_nf_bin
             "momentum reduction");
   return ABACUS_NF_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int abacus_nf_forces_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
                          double* acc, uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
@@ -691,6 +790,8 @@ const char* abacus_nf_strerror(int code) {
     case ABACUS_NF_EINVAL: return "invalid argument";
     case ABACUS_NF_ERANGE: return "size out of range (particles or cells reach 2^31)";
     case ABACUS_NF_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case ABACUS_NF_ESCRATCH:
+      return "problem too large for the 64 MiB static scratch of abacus_nf_forces_noalloc";
     case ABACUS_NF_EHIP: {
       thread_local std::string msg;
       msg = "HIP error: " + g_last_hip_error;

@@ -58,9 +58,9 @@ WORKLOADS = {
 }
 # HBM traffic of the dominant kernel from rocprofv3 counter runs, kept beside
 # the profiles; used only while the kernel source is unchanged.
-TRAFFIC_FILES = {"C2": "profiles/hbm_traffic_clustered_N2M_K32.json"}
+TRAFFIC_FILES = {"C4": "profiles/hbm_traffic_c4_batch64.json"}
 # VALU instruction counters of the pair kernels, same rule.
-VALU_FILES = {}
+VALU_FILES = {"C4": "profiles/valu_counters_c4_batch64.json"}
 KERNEL_SOURCES = {"forward": "paper_2110_11392_amd/csrc/pairs.hip",
                   "adjoint": "paper_2110_11392_amd/csrc/vjp.hip"}
 

@@ -758,7 +758,8 @@ MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
 }
 
 struct KdkLayout {
-  size_t boxtab, sumsq, amax, part, total;
+  size_t boxtab, sumsq, amax, part, tile_part, tile_cell, total;
+  int64_t tiles;
 };
 
 KdkLayout kdk_layout(const Resolved& r) {
@@ -773,6 +774,9 @@ KdkLayout kdk_layout(const Resolved& r) {
   L.sumsq = take(sizeof(double) * (size_t)r.cells_total);
   L.amax = take(sizeof(double) * (size_t)r.cells_total);
   L.part = take(sizeof(double) * 3 * (size_t)r.kdk_chunks);
+  L.tiles = (r.n_total + kKdkTile - 1) / kKdkTile;
+  L.tile_part = take(sizeof(double) * 4 * (size_t)L.tiles);
+  L.tile_cell = take(sizeof(int32_t) * 2 * (size_t)L.tiles);
   L.total = o;
   return L;
 }
@@ -892,9 +896,13 @@ int abacus_nf_kick_drift(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   w.cell_sumsq = at<double>(ws, L.sumsq);
   w.cell_amax = at<double>(ws, L.amax);
   w.chunk_part = at<double>(ws, L.part);
+  w.tile_part = at<double>(ws, L.tile_part);
+  w.tile_cell = at<int32_t>(ws, L.tile_cell);
   w.chunks = r.kdk_chunks;
+  w.tiles = L.tiles;
   Timer t(5, s);
-  ANF_HIP(launch_kick_drift(dboxes, nboxes, r.cells_total, w, b->cell_offsets, b->perm, pos, vel,
+  ANF_HIP(launch_kick_drift(dboxes, nboxes, r.n_total, r.cells_total, w, b->cell_offsets, b->perm,
+                            pos, vel,
                             acc, cell_stats, box_stats, s),
           "kick-drift");
   t.done();

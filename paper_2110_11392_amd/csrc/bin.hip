@@ -15,28 +15,6 @@
 
 namespace anf {
 
-// |t| must stay below 2^30 so the unwrapped cell fits comfortably in int32.
-constexpr double kMaxCellCoord = 1073741824.0;
-
-struct CellCoord {
-  int c;        // periodic cell index in [0, K)
-  float off;    // offset from the cell centre, cell units
-  bool ok;
-};
-
-__device__ __forceinline__ CellCoord cell_coord(float x, double cpl, int K) {
-  CellCoord r;
-  const double t = (double)x * cpl;
-  r.ok = (t == t) && fabs(t) < kMaxCellCoord;  // false for NaN, +-inf, huge
-  if (!r.ok) { r.c = 0; r.off = 0.0f; return r; }
-  const double fl = floor(t);
-  int c = (int)fl % K;
-  if (c < 0) c += K;
-  r.c = c;
-  r.off = (float)(t - (fl + 0.5));
-  return r;
-}
-
 // Pass 1: global cell id per particle and key/value init.  (No per-cell
 // counting here: device-wide atomics on the counts of crowded cells cost more
 // than the whole radix sort; the offsets are found in the sorted keys instead.)

@@ -8,18 +8,27 @@
 // global v_rms and a_max, and N.  The velocity rms keeps the mean (the paper
 // does not subtract it).
 //
-// How it maps to CDNA4: the step is HBM-bound (about 64 bytes per particle),
-// so the layout of the traffic is what matters.  One wave per cell (a
-// persistent loop over cells): lanes stride over the cell's sorted slots and
-// gather the particle through the permutation, so every lane of a cell adds to
-// the same statistics and the wave reduces them with DPP moves in a fixed
-// order -- no atomics, and run-to-run identical results.  When the caller keeps particles
-// in cell order (as the slabs of the paper's code do), the gathers are
-// contiguous.  The per-box statistics are a two-level, fixed-order reduction
-// over chunks of 512 cells.
+// How it maps to CDNA4: the step is HBM-bound (64 bytes per particle), so what
+// matters is that every wave keeps many independent loads in flight.  The
+// update is flat over the sorted slots: a block owns a tile of kKdkTile
+// consecutive slots, each thread four of them at a stride of the block size
+// (consecutive lanes, consecutive slots), with all of its gathers through the
+// permutation issued before any arithmetic.  Cells are runs of consecutive
+// slots; a slot's cell is recomputed from its position before the drift with
+// the binning's own rule.  The per-cell statistics are a segmented reduction
+// in a fixed order: inside the tile each run is summed by one wave (lanes
+// strided over the run, then a fixed DPP tree), and a run cut by tile
+// boundaries leaves its pieces' partials per tile, which one thread per cell
+// adds in tile order afterwards.  No atomics, so every result is run-to-run
+// identical.  When the caller keeps particles in cell order (as the slabs of
+// the paper's code do) the gathers are contiguous.  The per-box statistics
+// are a two-level, fixed-order reduction over chunks of 512 cells.
 #include "nf_internal.h"
 
 namespace anf {
+
+constexpr int kKdkThreads = 256;
+constexpr int kKdkPer = kKdkTile / kKdkThreads;  // slots per thread
 
 __device__ __forceinline__ int find_box_by_chunk(const DevBox* __restrict__ boxes, int nb,
                                                  int64_t k) {
@@ -43,83 +52,189 @@ __device__ __forceinline__ float wrap_coord(double t, double L) {
   return f;
 }
 
-__global__ __launch_bounds__(256) void k_kick_drift(const DevBox* __restrict__ boxes, int nboxes,
-                                                    int64_t cells_total,
-                                                    const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ perm,
-                                                    float* __restrict__ pos,
-                                                    float* __restrict__ vel,
-                                                    const float* __restrict__ acc,
-                                                    double* __restrict__ cell_sumsq,
-                                                    double* __restrict__ cell_amax,
-                                                    double* __restrict__ cell_stats) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  // The next cell's slot range is requested before this cell's particles are
-  // processed, so its latency overlaps them.
-  int nbeg = 0, nend = 0;
-  if (wave < cells_total) {
-    nbeg = __builtin_amdgcn_readfirstlane(off[wave]);
-    nend = __builtin_amdgcn_readfirstlane(off[wave + 1]);
-  }
-  for (int64_t c = wave; c < cells_total; c += nwaves) {
-    const int beg = nbeg, end = nend;
-    if (c + nwaves < cells_total) {
-      nbeg = __builtin_amdgcn_readfirstlane(off[c + nwaves]);
-      nend = __builtin_amdgcn_readfirstlane(off[c + nwaves + 1]);
-    }
-    const int b = nboxes == 1 ? 0 : find_box_by_cell(boxes, nboxes, c);
-    const double kick = boxes[b].kick, drift = boxes[b].drift, L = boxes[b].box_len;
-    double s2 = 0.0, am = 0.0;
-    for (int s = beg + lane; s < end; s += 64) {
-      const int64_t i = perm[s];
-      const float ax = acc[3 * i], ay = acc[3 * i + 1], az = acc[3 * i + 2];
-      const float vx = (float)((double)vel[3 * i] + kick * (double)ax);
-      const float vy = (float)((double)vel[3 * i + 1] + kick * (double)ay);
-      const float vz = (float)((double)vel[3 * i + 2] + kick * (double)az);
-      vel[3 * i] = vx;
-      vel[3 * i + 1] = vy;
-      vel[3 * i + 2] = vz;
-      pos[3 * i] = wrap_coord((double)pos[3 * i] + drift * (double)vx, L);
-      pos[3 * i + 1] = wrap_coord((double)pos[3 * i + 1] + drift * (double)vy, L);
-      pos[3 * i + 2] = wrap_coord((double)pos[3 * i + 2] + drift * (double)vz, L);
-      s2 += ((double)vx * (double)vx + (double)vy * (double)vy) + (double)vz * (double)vz;
-      const double a2 = ((double)ax * (double)ax + (double)ay * (double)ay) + (double)az * (double)az;
-      const double a = sqrt(a2);
-      am = a > am ? a : am;
-    }
-    // Sum and maximum over the wave with DPP moves in a fixed pattern (quad
-    // permutes, half-row and row mirrors, then the row broadcasts into rows 1
-    // and 3 and into rows 2 and 3); lane 63 ends with both totals.  Lanes of
-    // rows a broadcast does not write add 0, and 0 <= |a| leaves the maximum.
-    {
-      double o;
-      o = dpp_f64<0xB1, 0xF>(s2); s2 += o; o = dpp_f64<0xB1, 0xF>(am); am = o > am ? o : am;
-      o = dpp_f64<0x4E, 0xF>(s2); s2 += o; o = dpp_f64<0x4E, 0xF>(am); am = o > am ? o : am;
-      o = dpp_f64<0x141, 0xF>(s2); s2 += o; o = dpp_f64<0x141, 0xF>(am); am = o > am ? o : am;
-      o = dpp_f64<0x140, 0xF>(s2); s2 += o; o = dpp_f64<0x140, 0xF>(am); am = o > am ? o : am;
-      o = dpp_f64<0x142, 0xA>(s2); s2 += o; o = dpp_f64<0x142, 0xA>(am); am = o > am ? o : am;
-      o = dpp_f64<0x143, 0xC>(s2); s2 += o; o = dpp_f64<0x143, 0xC>(am); am = o > am ? o : am;
-    }
-    if (lane == 63) {
-      cell_sumsq[c] = s2;
-      cell_amax[c] = am;
-      if (cell_stats) {
-        const int n = end - beg;
-        cell_stats[2 * c] = n > 0 ? sqrt(s2 / (double)n) : 0.0;
-        cell_stats[2 * c + 1] = am;
-      }
-    }
+// Sum and maximum over the wave with DPP moves in a fixed pattern (quad
+// permutes, half-row and row mirrors, then the row broadcasts into rows 1 and
+// 3 and into rows 2 and 3); lane 63 ends with both totals.  Lanes of rows a
+// broadcast does not write add 0, and 0 <= |a| leaves the maximum.
+__device__ __forceinline__ void wave_sum_max(double& s2, double& am) {
+  double o;
+  o = dpp_f64<0xB1, 0xF>(s2); s2 += o; o = dpp_f64<0xB1, 0xF>(am); am = o > am ? o : am;
+  o = dpp_f64<0x4E, 0xF>(s2); s2 += o; o = dpp_f64<0x4E, 0xF>(am); am = o > am ? o : am;
+  o = dpp_f64<0x141, 0xF>(s2); s2 += o; o = dpp_f64<0x141, 0xF>(am); am = o > am ? o : am;
+  o = dpp_f64<0x140, 0xF>(s2); s2 += o; o = dpp_f64<0x140, 0xF>(am); am = o > am ? o : am;
+  o = dpp_f64<0x142, 0xA>(s2); s2 += o; o = dpp_f64<0x142, 0xA>(am); am = o > am ? o : am;
+  o = dpp_f64<0x143, 0xC>(s2); s2 += o; o = dpp_f64<0x143, 0xC>(am); am = o > am ? o : am;
+}
+
+__device__ __forceinline__ void write_cell(int64_t c, int64_t n, double s2, double am,
+                                           double* __restrict__ cell_sumsq,
+                                           double* __restrict__ cell_amax,
+                                           double* __restrict__ cell_stats) {
+  cell_sumsq[c] = s2;
+  cell_amax[c] = am;
+  if (cell_stats) {
+    cell_stats[2 * c] = sqrt(s2 / (double)n);
+    cell_stats[2 * c + 1] = am;
   }
 }
 
+__global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
+    const DevBox* __restrict__ boxes, int nboxes, int64_t n_total,
+    const int32_t* __restrict__ off, const int32_t* __restrict__ perm, float* __restrict__ pos,
+    float* __restrict__ vel, const float* __restrict__ acc, double* __restrict__ cell_sumsq,
+    double* __restrict__ cell_amax, double* __restrict__ cell_stats,
+    double* __restrict__ tile_part, int32_t* __restrict__ tile_cell) {
+  __shared__ double s_v2[kKdkTile], s_am[kKdkTile];
+  __shared__ int s_cell[kKdkTile];
+  __shared__ int s_run[kKdkTile + 1];
+  __shared__ int s_wave_runs[kKdkThreads / 64];
+  __shared__ int s_box[2];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t tile = blockIdx.x;
+  const int64_t tile0 = tile * kKdkTile;
+  const int len = n_total - tile0 < kKdkTile ? (int)(n_total - tile0) : kKdkTile;
+  if (t == 0) {
+    s_box[0] = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, tile0);
+    s_box[1] = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, tile0 + len - 1);
+  }
+  __syncthreads();
+  const int box_lo = s_box[0], box_hi = s_box[1];
+
+  // ---- the update: every gather first, then the arithmetic ---------------
+  int64_t idx[kKdkPer];
+#pragma unroll
+  for (int k = 0; k < kKdkPer; ++k) {
+    const int j = k * kKdkThreads + t;
+    idx[k] = j < len ? (int64_t)perm[tile0 + j] : -1;
+  }
+  float ax[kKdkPer], ay[kKdkPer], az[kKdkPer], vx[kKdkPer], vy[kKdkPer], vz[kKdkPer];
+  float px[kKdkPer], py[kKdkPer], pz[kKdkPer];
+#pragma unroll
+  for (int k = 0; k < kKdkPer; ++k) {
+    const int64_t i = idx[k] < 0 ? 0 : idx[k];
+    ax[k] = acc[3 * i]; ay[k] = acc[3 * i + 1]; az[k] = acc[3 * i + 2];
+    vx[k] = vel[3 * i]; vy[k] = vel[3 * i + 1]; vz[k] = vel[3 * i + 2];
+    px[k] = pos[3 * i]; py[k] = pos[3 * i + 1]; pz[k] = pos[3 * i + 2];
+  }
+#pragma unroll
+  for (int k = 0; k < kKdkPer; ++k) {
+    const int j = k * kKdkThreads + t;
+    if (j >= len) continue;
+    const int64_t i = idx[k];
+    const int b = box_lo == box_hi ? box_lo : find_box_by_first(boxes, nboxes, tile0 + j);
+    const DevBox& B = boxes[b];
+    const double kick = B.kick, drift = B.drift, L = B.box_len, cpl = B.cells_per_len;
+    const int K = B.K;
+    // the slot's cell: the binning's rule on the position before the drift
+    const CellCoord cx = cell_coord(px[k], cpl, K), cy = cell_coord(py[k], cpl, K),
+                    cz = cell_coord(pz[k], cpl, K);
+    s_cell[j] = B.cell_base + (cx.c * K + cy.c) * K + cz.c;
+    const float nvx = (float)((double)vx[k] + kick * (double)ax[k]);
+    const float nvy = (float)((double)vy[k] + kick * (double)ay[k]);
+    const float nvz = (float)((double)vz[k] + kick * (double)az[k]);
+    vel[3 * i] = nvx;
+    vel[3 * i + 1] = nvy;
+    vel[3 * i + 2] = nvz;
+    pos[3 * i] = wrap_coord((double)px[k] + drift * (double)nvx, L);
+    pos[3 * i + 1] = wrap_coord((double)py[k] + drift * (double)nvy, L);
+    pos[3 * i + 2] = wrap_coord((double)pz[k] + drift * (double)nvz, L);
+    s_v2[j] = ((double)nvx * (double)nvx + (double)nvy * (double)nvy) + (double)nvz * (double)nvz;
+    const double a2 =
+        ((double)ax[k] * (double)ax[k] + (double)ay[k] * (double)ay[k]) + (double)az[k] * (double)az[k];
+    s_am[j] = sqrt(a2);
+  }
+  __syncthreads();
+
+  // ---- runs of equal cells: their starts, compacted in slot order ----------
+  // Thread t owns slots [kKdkPer t, kKdkPer t + kKdkPer) of the tile here.
+  int starts = 0;
+#pragma unroll
+  for (int k = 0; k < kKdkPer; ++k) {
+    const int j = kKdkPer * t + k;
+    starts += (j < len && (j == 0 || s_cell[j] != s_cell[j - 1])) ? 1 : 0;
+  }
+  int incl = starts;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  if (lane == 63) s_wave_runs[wv] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wv; ++w) base += s_wave_runs[w];
+  const int nruns = s_wave_runs[0] + s_wave_runs[1] + s_wave_runs[2] + s_wave_runs[3];
+  int at = base + incl - starts;
+#pragma unroll
+  for (int k = 0; k < kKdkPer; ++k) {
+    const int j = kKdkPer * t + k;
+    if (j < len && (j == 0 || s_cell[j] != s_cell[j - 1])) s_run[at++] = j;
+  }
+  if (t == 0) s_run[nruns] = len;
+  __syncthreads();
+
+  // ---- each run summed by one wave; whole cells written, cut ones kept ----
+  for (int r = wv; r < nruns; r += kKdkThreads / 64) {
+    const int rb = s_run[r], re = s_run[r + 1];
+    double s2 = 0.0, am = 0.0;
+    for (int j = rb + lane; j < re; j += 64) {
+      s2 += s_v2[j];
+      am = s_am[j] > am ? s_am[j] : am;
+    }
+    wave_sum_max(s2, am);
+    if (lane == 63) {
+      const int64_t c = s_cell[rb];
+      const int64_t cb = off[c], ce = off[c + 1];
+      const bool head = cb < tile0, tail = ce > tile0 + len;
+      if (!head && !tail) write_cell(c, ce - cb, s2, am, cell_sumsq, cell_amax, cell_stats);
+      if (head) {
+        tile_part[4 * tile] = s2;
+        tile_part[4 * tile + 1] = am;
+      }
+      if (tail) {
+        tile_part[4 * tile + 2] = s2;
+        tile_part[4 * tile + 3] = am;
+      }
+    }
+  }
+  if (t == 0) {
+    tile_cell[2 * tile] = s_cell[0];
+    tile_cell[2 * tile + 1] = s_cell[len - 1];
+  }
+}
+
+// Cells cut by tile boundaries: the thread of boundary q (between tiles q - 1
+// and q) owns the cell of tile q - 1's last slot if that cell starts inside
+// tile q - 1 and continues past the boundary; it adds the cell's piece in tile
+// q - 1 and then the pieces in the following tiles, in order.
+__global__ __launch_bounds__(256) void k_kdk_cut_cells(
+    int64_t tiles, const int32_t* __restrict__ off, const double* __restrict__ tile_part,
+    const int32_t* __restrict__ tile_cell, double* __restrict__ cell_sumsq,
+    double* __restrict__ cell_amax, double* __restrict__ cell_stats) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (q >= tiles) return;
+  const int64_t c = tile_cell[2 * (q - 1) + 1];
+  const int64_t cb = off[c], ce = off[c + 1];
+  const int64_t bound = q * (int64_t)kKdkTile;
+  if (!(ce > bound && cb >= bound - kKdkTile)) return;
+  double s2 = tile_part[4 * (q - 1) + 2], am = tile_part[4 * (q - 1) + 3];
+  for (int64_t u = q; u < tiles; ++u) {
+    s2 += tile_part[4 * u];
+    const double m = tile_part[4 * u + 1];
+    am = m > am ? m : am;
+    if (ce <= (u + 1) * (int64_t)kKdkTile) break;
+  }
+  write_cell(c, ce - cb, s2, am, cell_sumsq, cell_amax, cell_stats);
+}
+
 // Stage 1: chunk k of a box -> (min over its cells of v_rms/a_max, sum |v'|^2,
-// max |a|), reduced across the block in a fixed tree order.
+// max |a|), reduced across the block in a fixed tree order.  Empty cells count
+// as zero and get their zero statistics here.
 __global__ __launch_bounds__(256) void k_kdk_chunks(const DevBox* __restrict__ boxes, int nboxes,
                                                     const int32_t* __restrict__ off,
                                                     const double* __restrict__ cell_sumsq,
                                                     const double* __restrict__ cell_amax,
+                                                    double* __restrict__ cell_stats,
                                                     double* __restrict__ part) {
   __shared__ double s_min[256], s_sum[256], s_max[256];
   const int64_t k = blockIdx.x;
@@ -131,7 +246,12 @@ __global__ __launch_bounds__(256) void k_kdk_chunks(const DevBox* __restrict__ b
   double mn = __builtin_inf(), sm = 0.0, mx = 0.0;
   for (int64_t c = first + threadIdx.x; c < last; c += blockDim.x) {
     const int n = off[c + 1] - off[c];
-    const double s2 = cell_sumsq[c], am = cell_amax[c];
+    // the update writes occupied cells only
+    const double s2 = n > 0 ? cell_sumsq[c] : 0.0, am = n > 0 ? cell_amax[c] : 0.0;
+    if (n == 0 && cell_stats) {
+      cell_stats[2 * c] = 0.0;
+      cell_stats[2 * c + 1] = 0.0;
+    }
     sm += s2;
     mx = am > mx ? am : mx;
     if (n > 0 && am > 0.0) {
@@ -197,22 +317,27 @@ __global__ __launch_bounds__(256) void k_kdk_boxes(const DevBox* __restrict__ bo
   }
 }
 
-hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t cells_total,
-                             const KdkWork& w, const int32_t* off, const int32_t* perm,
-                             float* pos, float* vel, const float* acc, double* cell_stats,
-                             double* box_stats, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&k_kick_drift);
-  int64_t blocks = persistent_blocks(fn, 256);
-  const int64_t need = (cells_total + 3) / 4;  // four waves (cells) per block
-  if (blocks > need) blocks = need > 0 ? need : 1;
-  hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)blocks), dim3(256), 0, s, boxes, nboxes,
-                     cells_total, off, perm, pos, vel, acc, w.cell_sumsq, w.cell_amax,
-                     cell_stats);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !box_stats) return e;
+hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t n_total,
+                             int64_t cells_total, const KdkWork& w, const int32_t* off,
+                             const int32_t* perm, float* pos, float* vel, const float* acc,
+                             double* cell_stats, double* box_stats, hipStream_t s) {
+  hipError_t e;
+  if (w.tiles > 0) {
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)w.tiles), dim3(kKdkThreads), 0, s, boxes,
+                       nboxes, n_total, off, perm, pos, vel, acc, w.cell_sumsq, w.cell_amax,
+                       cell_stats, w.tile_part, w.tile_cell);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (w.tiles > 1) {
+      hipLaunchKernelGGL(k_kdk_cut_cells, dim3((unsigned)((w.tiles - 1 + 255) / 256)), dim3(256),
+                         0, s, w.tiles, off, w.tile_part, w.tile_cell, w.cell_sumsq, w.cell_amax,
+                         cell_stats);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if (!cell_stats && !box_stats) return hipSuccess;
   hipLaunchKernelGGL(k_kdk_chunks, dim3((unsigned)w.chunks), dim3(256), 0, s, boxes, nboxes, off,
-                     w.cell_sumsq, w.cell_amax, w.chunk_part);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+                     w.cell_sumsq, w.cell_amax, cell_stats, w.chunk_part);
+  if ((e = hipGetLastError()) != hipSuccess || !box_stats) return e;
   hipLaunchKernelGGL(k_kdk_boxes, dim3((unsigned)nboxes), dim3(256), 0, s, boxes, w.chunk_part,
                      box_stats);
   return hipGetLastError();

@@ -155,6 +155,32 @@ __device__ __forceinline__ int find_box_by_cell(const DevBox* __restrict__ boxes
   return lo;
 }
 
+// Cell assignment of one FP32 coordinate (the binning's rule, also used by the
+// kick-drift statistics to find a sorted slot's cell): t = x * (K/L) in FP64,
+// the periodic index floor(t) mod K and the offset t - (floor(t) + 1/2)
+// rounded once to FP32.  |t| must stay below 2^30 so the unwrapped cell fits
+// comfortably in int32.  Files including this are built without contraction.
+constexpr double kMaxCellCoord = 1073741824.0;
+
+struct CellCoord {
+  int c;        // periodic cell index in [0, K)
+  float off;    // offset from the cell centre, cell units
+  bool ok;
+};
+
+__device__ __forceinline__ CellCoord cell_coord(float x, double cpl, int K) {
+  CellCoord r;
+  const double t = (double)x * cpl;
+  r.ok = (t == t) && fabs(t) < kMaxCellCoord;  // false for NaN, +-inf, huge
+  if (!r.ok) { r.c = 0; r.off = 0.0f; return r; }
+  const double fl = floor(t);
+  int c = (int)fl % K;
+  if (c < 0) c += K;
+  r.c = c;
+  r.off = (float)(t - (fl + 0.5));
+  return r;
+}
+
 // ---- launch helpers implemented in the .hip files (host side) -------------
 
 // common.hip
@@ -191,13 +217,18 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
 
 // kdk.hip
 constexpr int kKdkChunk = 512;   // cells per statistics chunk
+constexpr int kKdkTile = 1024;   // sorted slots per block of the update
 struct KdkWork {
-  double* cell_sumsq;   // cells_total: sum |v'|^2 per cell
-  double* cell_amax;    // cells_total: max |a| per cell
+  double* cell_sumsq;   // cells_total: sum |v'|^2 per occupied cell
+  double* cell_amax;    // cells_total: max |a| per occupied cell
   double* chunk_part;   // chunks x 3: min ratio, sum |v'|^2, max |a|
+  double* tile_part;    // tiles x 4: (sum, max) of the first and of the last run
+  int32_t* tile_cell;   // tiles x 2: cells of the first and of the last slot
   int64_t chunks;
+  int64_t tiles;
 };
-hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t cells_total,
+hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t n_total,
+                             int64_t cells_total,
                              const KdkWork& w, const int32_t* cell_offsets, const int32_t* perm,
                              float* pos, float* vel, const float* acc, double* cell_stats,
                              double* box_stats, hipStream_t s);

@@ -87,6 +87,7 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
   __shared__ double s_v2[kKdkTile], s_am[kKdkTile];
   __shared__ int s_cell[kKdkTile];
   __shared__ int s_run[kKdkTile + 1];
+  __shared__ int s_cb[kKdkTile], s_ce[kKdkTile];  // each run's cell: first and end slot
   __shared__ int s_wave_runs[kKdkThreads / 64];
   __shared__ int s_box[2];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -172,6 +173,14 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
   }
   if (t == 0) s_run[nruns] = len;
   __syncthreads();
+  // every run's cell extent, all fetched at once (one round trip for the tile
+  // instead of one per run)
+  for (int r = t; r < nruns; r += kKdkThreads) {
+    const int64_t c = s_cell[s_run[r]];
+    s_cb[r] = off[c];
+    s_ce[r] = off[c + 1];
+  }
+  __syncthreads();
 
   // ---- each run summed by one wave; whole cells written, cut ones kept ----
   for (int r = wv; r < nruns; r += kKdkThreads / 64) {
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
     wave_sum_max(s2, am);
     if (lane == 63) {
       const int64_t c = s_cell[rb];
-      const int64_t cb = off[c], ce = off[c + 1];
+      const int64_t cb = s_cb[r], ce = s_ce[r];
       const bool head = cb < tile0, tail = ce > tile0 + len;
       if (!head && !tail) write_cell(c, ce - cb, s2, am, cell_sumsq, cell_amax, cell_stats);
       if (head) {

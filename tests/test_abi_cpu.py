@@ -272,3 +272,26 @@ def test_fp64_forces_arguments_without_gpu():
                                     None) == _lib.EINVAL
     assert lib.abacus_nf_forces_f64(b, 1, ctypes.byref(binned), fake, _lib.PLUMMER, None, nbytes,
                                     None) == _lib.EWORKSPACE
+
+
+def test_noalloc_forces_arguments_without_gpu():
+    """The no-allocation entry point validates like abacus_nf_forces and refuses
+    a problem its static scratch cannot hold, all before any HIP call."""
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x1000)
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    small = boxes((100, 1.0, 8, 2, 1e-3))
+    # bad arguments: unknown flag, two accumulation modes, no output, no pair counter
+    for flags, acc in ((0x80, fake), (_lib.SINGLE_ACC | _lib.CHUNKED, fake), (0, None),
+                       (_lib.COUNT_PAIRS, fake)):
+        assert lib.abacus_nf_forces_noalloc(small, 1, ctypes.byref(binned), acc, None, None,
+                                            None, flags, None) == _lib.EINVAL
+    # a bad box is rejected like everywhere else
+    assert lib.abacus_nf_forces_noalloc(boxes((100, 1.0, 4, 2, 1e-3)), 1, ctypes.byref(binned),
+                                        fake, None, None, None, 0, None) == _lib.EINVAL
+    # 16.8 M particles need far more than the 64 MiB scratch
+    big = boxes((16_777_216, 1.0, 64, 2, 1.0 / 10240.0))
+    rc = lib.abacus_nf_forces_noalloc(big, 1, ctypes.byref(binned), fake, None, None, None, 0,
+                                      None)
+    assert rc == _lib.ESCRATCH
+    assert "scratch" in _lib.strerror(rc)

@@ -154,47 +154,59 @@ def host_cpu():
     return model, nproc
 
 
-def accuracy_sample(boxes, acc, grad, wvec, n_sinks, seed):
-    """The timed outputs against the FP64 oracle on ~n_sinks sinks drawn in
-    proportion to N_b: the forces' per-particle fractional error (median,
-    99.9th percentile) and the adjoint's relative 2-norm error with its
-    per-particle median / 99.9th percentile.  The oracle calls themselves
-    (single thread, forces + adjoint of those sinks) are timed and give the
-    CPU baseline in the metric's unit."""
+def oracle_sample(boxes, wvec, n_sinks, seed):
+    """FP64 oracle forces and adjoint on ~n_sinks sinks drawn in proportion to
+    N_b (global indices into the concatenated particles), with the single-thread
+    time of those oracle calls: the CPU baseline in the metric's unit."""
     import numpy as np
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
     from paper_2110_11392_amd import synth
     n_all = sum(b.n for b in boxes)
-    got_a, got_g, ref_a, ref_g = [], [], [], []
-    pairs, n_done, dt = 0, 0, 0.0
+    idx, ref_a, ref_g = [], [], []
+    pairs, dt = 0, 0.0
     first = 0
     for k, b in enumerate(boxes):
         m = min(b.n, max(1, int(round(n_sinks * b.n / n_all)))) if b.n else 0
         if m:
             s = synth.sample_indices(b.n, m, seed + k)
-            wb = wvec[first:first + b.n]
             t0 = time.perf_counter()
             ra, npairs = oracle.forces(b.pos, b.box, b.cpd, b.radius, b.eps_plummer, s)
-            rg = oracle.vjp(b.pos, wb, b.box, b.cpd, b.radius, b.eps_plummer, s)
+            rg = oracle.vjp(b.pos, wvec[first:first + b.n], b.box, b.cpd, b.radius,
+                            b.eps_plummer, s)
             dt += time.perf_counter() - t0
             pairs += 2 * npairs
-            n_done += s.size
+            idx.append(first + s)
             ref_a.append(ra)
             ref_g.append(rg)
-            got_a.append(acc[first + s].astype(np.float64))
-            got_g.append(grad[first + s].astype(np.float64))
         first += b.n
-    a, ra = np.concatenate(got_a), np.concatenate(ref_a)
-    g, rg = np.concatenate(got_g), np.concatenate(ref_g)
+    idx = np.concatenate(idx)
+    model, nproc = host_cpu()
+    baseline = {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
+                "sample": f"the accuracy sample: {idx.size} sinks of the same workload drawn in "
+                          f"proportion to N_b, FP64 forces + adjoint of those sinks, {pairs} pair "
+                          f"evaluations in {dt:.1f} s on one thread (including the oracle's "
+                          f"binning of each sampled box)",
+                "cpu_model": model, "host_cores_available": nproc}
+    return (idx, np.concatenate(ref_a), np.concatenate(ref_g)), baseline
+
+
+def accuracy(sample, acc, grad, seed):
+    """Per-particle fractional force error (median, 99.9th percentile) and the
+    adjoint's relative 2-norm error with its per-particle median / 99.9th
+    percentile, of outputs `acc`, `grad` (all particles) on the oracle sample."""
+    import numpy as np
+    idx, ra, rg = sample
+    a = acc[idx].astype(np.float64)
+    g = grad[idx].astype(np.float64)
     nrm = np.linalg.norm(ra, axis=1)
     keep = nrm > 0
     e = np.linalg.norm(a[keep] - ra[keep], axis=1) / nrm[keep]
     gn = np.linalg.norm(rg, axis=1)
     gkeep = gn > 0
     ge = np.linalg.norm(g[gkeep] - rg[gkeep], axis=1) / gn[gkeep]
-    accuracy = {
-        "sinks": int(n_done), "sampling": f"in proportion to N_b, seeds {seed}+b",
+    return {
+        "sinks": int(idx.size), "sampling": f"in proportion to N_b, seeds {seed}+b",
         "force_frac_err_median": float(np.median(e)),
         "force_frac_err_p999": float(np.percentile(e, 99.9)),
         "adjoint_rel_err": float(np.linalg.norm(g - rg) / np.linalg.norm(rg)),
@@ -202,14 +214,6 @@ def accuracy_sample(boxes, acc, grad, wvec, n_sinks, seed):
         "adjoint_frac_err_p999": float(np.percentile(ge, 99.9)),
         "tolerances": {"force_median": 1e-6, "force_p999": 1e-4, "adjoint_rel": 1e-4},
     }
-    model, nproc = host_cpu()
-    baseline = {"value": pairs / dt / 1e9, "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
-                "sample": f"the accuracy sample: {n_done} sinks of the same workload drawn in "
-                          f"proportion to N_b, FP64 forces + adjoint of those sinks, {pairs} pair "
-                          f"evaluations in {dt:.1f} s on one thread (including the oracle's "
-                          f"binning of each sampled box)",
-                "cpu_model": model, "host_cores_available": nproc}
-    return accuracy, baseline
 
 
 class Stepper:
@@ -491,6 +495,7 @@ def main():
     mom_out = st.mom.cpu().numpy()
 
     sequential_ms = None
+    plain = None
     if args.workload == "C4":
         log("[bench] 64 sequential per-box calls, built-in shapes, no graph")
         per_box = []
@@ -508,6 +513,26 @@ def main():
         torch.cuda.synchronize()
         sequential_ms = timed(torch, sequential, args.steps)
         log(f"[bench] sequential {sequential_ms:.3f} ms/step")
+        # the plain single-box path: the same calls with one FP32 running sum
+        # per sink (the paper kernel's accumulation), built-in shapes
+        for s in per_box:
+            s.accumulation = "single"
+        sequential()
+        torch.cuda.synchronize()
+        anf.timing_reset()
+        anf.timing_enable(True)
+        plain_ms = timed(torch, sequential, args.steps)
+        anf.timing_enable(False)
+        pk = {name: anf.timing_read(k)[0] / args.steps for name, k in
+              (("forward", 0), ("adjoint", 1), ("bin", 2), ("plan", 3))}
+        plain = {"accumulation": "single", "shapes": "built-in", "calls": "64 per-box calls per step",
+                 "ms_per_step": plain_ms, "value": 2.0 * pairs / (plain_ms * 1e-3) / 1e9,
+                 "kernel_ms_per_step": pk,
+                 "adjoint_frac_fp32": FLOP_ADJ * pairs / (pk["adjoint"] * 1e-3) / 1e12
+                 / PEAK_FP32_TFLOPS}
+        plain_acc = torch.cat([s.acc for s in per_box]).cpu().numpy()
+        plain_grad = torch.cat([s.grad for s in per_box]).cpu().numpy()
+        log(f"[bench] plain single-box {plain_ms:.3f} ms/step")
         del per_box
 
     resid = float((np.abs(mom_out[:, :3]).max(axis=1) / mom_out[:, 3]).max())
@@ -558,13 +583,16 @@ def main():
     if sequential_ms is not None:
         out["sequential_per_box_ms_per_step"] = sequential_ms
         out["batched_speedup_vs_sequential"] = sequential_ms / ms_value
+    if plain is not None:
+        out["plain_single_box"] = plain
     if not args.no_cpu_baseline:
         log(f"[bench] oracle comparison of the timed outputs on {args.accuracy_sinks} sinks")
-        accuracy, baseline = accuracy_sample(boxes, acc_out, grad_out,
-                                             st.wvec.cpu().numpy(), args.accuracy_sinks, 4250)
-        out["accuracy"] = accuracy
+        sample, baseline = oracle_sample(boxes, st.wvec.cpu().numpy(), args.accuracy_sinks, 4250)
+        out["accuracy"] = accuracy(sample, acc_out, grad_out, 4250)
         out["cpu_baseline"] = baseline
-        log(f"[bench] accuracy {accuracy}")
+        if plain is not None:
+            plain["accuracy"] = accuracy(sample, plain_acc, plain_grad, 4250)
+        log(f"[bench] accuracy {out['accuracy']}")
     rows_src = (st, boxes)
     if not args.no_configs:
         out["configs"] = {}

@@ -758,7 +758,7 @@ MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
 }
 
 struct KdkLayout {
-  size_t boxtab, sumsq, amax, part, tile_part, tile_cell, total;
+  size_t boxtab, sumsq, amax, part, tile_part, total;
   int64_t tiles;
 };
 
@@ -776,7 +776,6 @@ KdkLayout kdk_layout(const Resolved& r) {
   L.part = take(sizeof(double) * 3 * (size_t)r.kdk_chunks);
   L.tiles = (r.n_total + kKdkTile - 1) / kKdkTile;
   L.tile_part = take(sizeof(double) * 4 * (size_t)L.tiles);
-  L.tile_cell = take(sizeof(int32_t) * 2 * (size_t)L.tiles);
   L.total = o;
   return L;
 }
@@ -897,7 +896,6 @@ int abacus_nf_kick_drift(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   w.cell_amax = at<double>(ws, L.amax);
   w.chunk_part = at<double>(ws, L.part);
   w.tile_part = at<double>(ws, L.tile_part);
-  w.tile_cell = at<int32_t>(ws, L.tile_cell);
   w.chunks = r.kdk_chunks;
   w.tiles = L.tiles;
   Timer t(5, s);

@@ -11,14 +11,16 @@
 // How it maps to CDNA4: the step is HBM-bound (64 bytes per particle), so what
 // matters is that every wave keeps many independent loads in flight.  The
 // update is flat over the sorted slots: a block owns a tile of kKdkTile
-// consecutive slots, each thread four of them at a stride of the block size
+// consecutive slots, each thread kKdkPer of them at a stride of the block size
 // (consecutive lanes, consecutive slots), with all of its gathers through the
-// permutation issued before any arithmetic.  Cells are runs of consecutive
+// permutation issued before any arithmetic.  Small tiles keep the block's
+// registers and LDS low, so that many blocks per CU have loads in flight
+// while others reduce.  Cells are runs of consecutive
 // slots; a slot's cell is recomputed from its position before the drift with
 // the binning's own rule.  The per-cell statistics are a segmented reduction
 // in a fixed order: inside the tile each run is summed by one wave (lanes
 // strided over the run, then a fixed DPP tree), and a run cut by tile
-// boundaries leaves its pieces' partials per tile, which one thread per cell
+// boundaries leaves its pieces' partials per tile, which the statistics pass
 // adds in tile order afterwards.  No atomics, so every result is run-to-run
 // identical.  When the caller keeps particles in cell order (as the slabs of
 // the paper's code do) the gathers are contiguous.  The per-box statistics
@@ -41,12 +43,17 @@ __device__ __forceinline__ int find_box_by_chunk(const DevBox* __restrict__ boxe
 }
 
 // Periodic wrap of an FP64 coordinate into [0, L), rounded to FP32 (a value
-// that rounds up to L becomes 0).
+// that rounds up to L becomes 0).  Inside (0, L) the reduction below returns t
+// itself (q is 0, or 1 when t / L rounds up, and then t - L + L is exact), so
+// only coordinates that left the box take the division.
 __device__ __forceinline__ float wrap_coord(double t, double L) {
-  const double q = floor(t / L);
-  double r = t - q * L;
-  if (r < 0.0) r += L;
-  if (r >= L) r -= L;
+  double r = t;
+  if (!(t > 0.0 && t < L)) {
+    const double q = floor(t / L);
+    r = t - q * L;
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+  }
   float f = (float)r;
   if (f >= (float)L) f = 0.0f;
   return f;
@@ -55,21 +62,22 @@ __device__ __forceinline__ float wrap_coord(double t, double L) {
 // Sum and maximum over the wave with DPP moves in a fixed pattern (quad
 // permutes, half-row and row mirrors, then the row broadcasts into rows 1 and
 // 3 and into rows 2 and 3); lane 63 ends with both totals.  Lanes of rows a
-// broadcast does not write add 0, and 0 <= |a| leaves the maximum.
-__device__ __forceinline__ void wave_sum_max(double& s2, double& am) {
+// broadcast does not write add 0, and 0 <= |a|^2 leaves the maximum.
+__device__ __forceinline__ void wave_sum_max(double& s2, double& am2) {
   double o;
-  o = dpp_f64<0xB1, 0xF>(s2); s2 += o; o = dpp_f64<0xB1, 0xF>(am); am = o > am ? o : am;
-  o = dpp_f64<0x4E, 0xF>(s2); s2 += o; o = dpp_f64<0x4E, 0xF>(am); am = o > am ? o : am;
-  o = dpp_f64<0x141, 0xF>(s2); s2 += o; o = dpp_f64<0x141, 0xF>(am); am = o > am ? o : am;
-  o = dpp_f64<0x140, 0xF>(s2); s2 += o; o = dpp_f64<0x140, 0xF>(am); am = o > am ? o : am;
-  o = dpp_f64<0x142, 0xA>(s2); s2 += o; o = dpp_f64<0x142, 0xA>(am); am = o > am ? o : am;
-  o = dpp_f64<0x143, 0xC>(s2); s2 += o; o = dpp_f64<0x143, 0xC>(am); am = o > am ? o : am;
+  o = dpp_f64<0xB1, 0xF>(s2); s2 += o; o = dpp_f64<0xB1, 0xF>(am2); am2 = o > am2 ? o : am2;
+  o = dpp_f64<0x4E, 0xF>(s2); s2 += o; o = dpp_f64<0x4E, 0xF>(am2); am2 = o > am2 ? o : am2;
+  o = dpp_f64<0x141, 0xF>(s2); s2 += o; o = dpp_f64<0x141, 0xF>(am2); am2 = o > am2 ? o : am2;
+  o = dpp_f64<0x140, 0xF>(s2); s2 += o; o = dpp_f64<0x140, 0xF>(am2); am2 = o > am2 ? o : am2;
+  o = dpp_f64<0x142, 0xA>(s2); s2 += o; o = dpp_f64<0x142, 0xA>(am2); am2 = o > am2 ? o : am2;
+  o = dpp_f64<0x143, 0xC>(s2); s2 += o; o = dpp_f64<0x143, 0xC>(am2); am2 = o > am2 ? o : am2;
 }
 
-__device__ __forceinline__ void write_cell(int64_t c, int64_t n, double s2, double am,
+__device__ __forceinline__ void write_cell(int64_t c, int64_t n, double s2, double am2,
                                            double* __restrict__ cell_sumsq,
                                            double* __restrict__ cell_amax,
                                            double* __restrict__ cell_stats) {
+  const double am = sqrt(am2);
   cell_sumsq[c] = s2;
   cell_amax[c] = am;
   if (cell_stats) {
@@ -83,11 +91,11 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
     const int32_t* __restrict__ off, const int32_t* __restrict__ perm, float* __restrict__ pos,
     float* __restrict__ vel, const float* __restrict__ acc, double* __restrict__ cell_sumsq,
     double* __restrict__ cell_amax, double* __restrict__ cell_stats,
-    double* __restrict__ tile_part, int32_t* __restrict__ tile_cell) {
+    double* __restrict__ tile_part) {
   __shared__ double s_v2[kKdkTile], s_am[kKdkTile];
   __shared__ int s_cell[kKdkTile];
   __shared__ int s_run[kKdkTile + 1];
-  __shared__ int s_cb[kKdkTile], s_ce[kKdkTile];  // each run's cell: first and end slot
+  __shared__ int s_edge[2];  // begin of the first slot's cell, end of the last slot's cell
   __shared__ int s_wave_runs[kKdkThreads / 64];
   __shared__ int s_box[2];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -121,6 +129,7 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
   for (int k = 0; k < kKdkPer; ++k) {
     const int j = k * kKdkThreads + t;
     if (j >= len) continue;
+    const bool edge_first = j == 0, edge_last = j == len - 1;
     const int64_t i = idx[k];
     const int b = box_lo == box_hi ? box_lo : find_box_by_first(boxes, nboxes, tile0 + j);
     const DevBox& B = boxes[b];
@@ -129,7 +138,13 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
     // the slot's cell: the binning's rule on the position before the drift
     const CellCoord cx = cell_coord(px[k], cpl, K), cy = cell_coord(py[k], cpl, K),
                     cz = cell_coord(pz[k], cpl, K);
-    s_cell[j] = B.cell_base + (cx.c * K + cy.c) * K + cz.c;
+    const int cj = B.cell_base + (cx.c * K + cy.c) * K + cz.c;
+    s_cell[j] = cj;
+    // only the tile's first and last runs can belong to cells that continue
+    // past the tile: the begin of the first slot's cell and the end of the
+    // last slot's cell tell
+    if (edge_first) s_edge[0] = off[cj];
+    if (edge_last) s_edge[1] = off[cj + 1];
     const float nvx = (float)((double)vx[k] + kick * (double)ax[k]);
     const float nvy = (float)((double)vy[k] + kick * (double)ay[k]);
     const float nvz = (float)((double)vz[k] + kick * (double)az[k]);
@@ -140,18 +155,20 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
     pos[3 * i + 1] = wrap_coord((double)py[k] + drift * (double)nvy, L);
     pos[3 * i + 2] = wrap_coord((double)pz[k] + drift * (double)nvz, L);
     s_v2[j] = ((double)nvx * (double)nvx + (double)nvy * (double)nvy) + (double)nvz * (double)nvz;
-    const double a2 =
+    // |a|^2: the square root is monotonic, so the cell's max |a| is the root
+    // of its max |a|^2, taken once per cell
+    s_am[j] =
         ((double)ax[k] * (double)ax[k] + (double)ay[k] * (double)ay[k]) + (double)az[k] * (double)az[k];
-    s_am[j] = sqrt(a2);
   }
   __syncthreads();
 
   // ---- runs of equal cells: their starts, compacted in slot order ----------
   // Thread t owns slots [kKdkPer t, kKdkPer t + kKdkPer) of the tile here.
+  const int j0 = kKdkPer * t;
   int starts = 0;
 #pragma unroll
   for (int k = 0; k < kKdkPer; ++k) {
-    const int j = kKdkPer * t + k;
+    const int j = j0 + k;
     starts += (j < len && (j == 0 || s_cell[j] != s_cell[j - 1])) ? 1 : 0;
   }
   int incl = starts;
@@ -162,87 +179,56 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
   }
   if (lane == 63) s_wave_runs[wv] = incl;
   __syncthreads();
-  int base = 0;
-  for (int w = 0; w < wv; ++w) base += s_wave_runs[w];
-  const int nruns = s_wave_runs[0] + s_wave_runs[1] + s_wave_runs[2] + s_wave_runs[3];
+  int base = 0, nruns = 0;
+#pragma unroll
+  for (int w = 0; w < kKdkThreads / 64; ++w) {
+    base += w < wv ? s_wave_runs[w] : 0;
+    nruns += s_wave_runs[w];
+  }
   int at = base + incl - starts;
 #pragma unroll
   for (int k = 0; k < kKdkPer; ++k) {
-    const int j = kKdkPer * t + k;
+    const int j = j0 + k;
     if (j < len && (j == 0 || s_cell[j] != s_cell[j - 1])) s_run[at++] = j;
   }
   if (t == 0) s_run[nruns] = len;
   __syncthreads();
-  // every run's cell extent, all fetched at once (one round trip for the tile
-  // instead of one per run)
-  for (int r = t; r < nruns; r += kKdkThreads) {
-    const int64_t c = s_cell[s_run[r]];
-    s_cb[r] = off[c];
-    s_ce[r] = off[c + 1];
-  }
-  __syncthreads();
-
   // ---- each run summed by one wave; whole cells written, cut ones kept ----
   for (int r = wv; r < nruns; r += kKdkThreads / 64) {
     const int rb = s_run[r], re = s_run[r + 1];
-    double s2 = 0.0, am = 0.0;
+    double s2 = 0.0, am2 = 0.0;
     for (int j = rb + lane; j < re; j += 64) {
       s2 += s_v2[j];
-      am = s_am[j] > am ? s_am[j] : am;
+      am2 = s_am[j] > am2 ? s_am[j] : am2;
     }
-    wave_sum_max(s2, am);
+    wave_sum_max(s2, am2);
     if (lane == 63) {
-      const int64_t c = s_cell[rb];
-      const int64_t cb = s_cb[r], ce = s_ce[r];
-      const bool head = cb < tile0, tail = ce > tile0 + len;
-      if (!head && !tail) write_cell(c, ce - cb, s2, am, cell_sumsq, cell_amax, cell_stats);
+      // a run between two others is a whole cell of re - rb particles
+      const bool head = r == 0 && s_edge[0] < tile0;
+      const bool tail = r == nruns - 1 && s_edge[1] > tile0 + len;
+      if (!head && !tail) write_cell(s_cell[rb], re - rb, s2, am2, cell_sumsq, cell_amax, cell_stats);
       if (head) {
         tile_part[4 * tile] = s2;
-        tile_part[4 * tile + 1] = am;
+        tile_part[4 * tile + 1] = am2;
       }
       if (tail) {
         tile_part[4 * tile + 2] = s2;
-        tile_part[4 * tile + 3] = am;
+        tile_part[4 * tile + 3] = am2;
       }
     }
   }
-  if (t == 0) {
-    tile_cell[2 * tile] = s_cell[0];
-    tile_cell[2 * tile + 1] = s_cell[len - 1];
-  }
-}
-
-// Cells cut by tile boundaries: the thread of boundary q (between tiles q - 1
-// and q) owns the cell of tile q - 1's last slot if that cell starts inside
-// tile q - 1 and continues past the boundary; it adds the cell's piece in tile
-// q - 1 and then the pieces in the following tiles, in order.
-__global__ __launch_bounds__(256) void k_kdk_cut_cells(
-    int64_t tiles, const int32_t* __restrict__ off, const double* __restrict__ tile_part,
-    const int32_t* __restrict__ tile_cell, double* __restrict__ cell_sumsq,
-    double* __restrict__ cell_amax, double* __restrict__ cell_stats) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
-  if (q >= tiles) return;
-  const int64_t c = tile_cell[2 * (q - 1) + 1];
-  const int64_t cb = off[c], ce = off[c + 1];
-  const int64_t bound = q * (int64_t)kKdkTile;
-  if (!(ce > bound && cb >= bound - kKdkTile)) return;
-  double s2 = tile_part[4 * (q - 1) + 2], am = tile_part[4 * (q - 1) + 3];
-  for (int64_t u = q; u < tiles; ++u) {
-    s2 += tile_part[4 * u];
-    const double m = tile_part[4 * u + 1];
-    am = m > am ? m : am;
-    if (ce <= (u + 1) * (int64_t)kKdkTile) break;
-  }
-  write_cell(c, ce - cb, s2, am, cell_sumsq, cell_amax, cell_stats);
 }
 
 // Stage 1: chunk k of a box -> (min over its cells of v_rms/a_max, sum |v'|^2,
 // max |a|), reduced across the block in a fixed tree order.  Empty cells count
-// as zero and get their zero statistics here.
+// as zero and get their zero statistics here.  A cell that spans tiles of the
+// update is finished here: its piece in its first tile (that tile's last run),
+// then its pieces in the following tiles (their first runs), in tile order.
 __global__ __launch_bounds__(256) void k_kdk_chunks(const DevBox* __restrict__ boxes, int nboxes,
                                                     const int32_t* __restrict__ off,
                                                     const double* __restrict__ cell_sumsq,
                                                     const double* __restrict__ cell_amax,
+                                                    const double* __restrict__ tile_part,
                                                     double* __restrict__ cell_stats,
                                                     double* __restrict__ part) {
   __shared__ double s_min[256], s_sum[256], s_max[256];
@@ -254,10 +240,29 @@ __global__ __launch_bounds__(256) void k_kdk_chunks(const DevBox* __restrict__ b
   const int64_t last = first + kKdkChunk < box_end ? first + kKdkChunk : box_end;
   double mn = __builtin_inf(), sm = 0.0, mx = 0.0;
   for (int64_t c = first + threadIdx.x; c < last; c += blockDim.x) {
-    const int n = off[c + 1] - off[c];
-    // the update writes occupied cells only
-    const double s2 = n > 0 ? cell_sumsq[c] : 0.0, am = n > 0 ? cell_amax[c] : 0.0;
-    if (n == 0 && cell_stats) {
+    const int64_t cb = off[c], ce = off[c + 1];
+    const int n = (int)(ce - cb);
+    double s2 = 0.0, am = 0.0;
+    if (n > 0) {
+      const int64_t tb = cb / kKdkTile, te = (ce - 1) / kKdkTile;
+      if (tb == te) {  // written by the update
+        s2 = cell_sumsq[c];
+        am = cell_amax[c];
+      } else {
+        s2 = tile_part[4 * tb + 2];
+        double am2 = tile_part[4 * tb + 3];
+        for (int64_t u = tb + 1; u <= te; ++u) {
+          s2 += tile_part[4 * u];
+          const double m = tile_part[4 * u + 1];
+          am2 = m > am2 ? m : am2;
+        }
+        am = sqrt(am2);
+        if (cell_stats) {
+          cell_stats[2 * c] = sqrt(s2 / (double)n);
+          cell_stats[2 * c + 1] = am;
+        }
+      }
+    } else if (cell_stats) {
       cell_stats[2 * c] = 0.0;
       cell_stats[2 * c + 1] = 0.0;
     }
@@ -334,18 +339,12 @@ hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t n_total,
   if (w.tiles > 0) {
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)w.tiles), dim3(kKdkThreads), 0, s, boxes,
                        nboxes, n_total, off, perm, pos, vel, acc, w.cell_sumsq, w.cell_amax,
-                       cell_stats, w.tile_part, w.tile_cell);
+                       cell_stats, w.tile_part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (w.tiles > 1) {
-      hipLaunchKernelGGL(k_kdk_cut_cells, dim3((unsigned)((w.tiles - 1 + 255) / 256)), dim3(256),
-                         0, s, w.tiles, off, w.tile_part, w.tile_cell, w.cell_sumsq, w.cell_amax,
-                         cell_stats);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
   }
   if (!cell_stats && !box_stats) return hipSuccess;
   hipLaunchKernelGGL(k_kdk_chunks, dim3((unsigned)w.chunks), dim3(256), 0, s, boxes, nboxes, off,
-                     w.cell_sumsq, w.cell_amax, cell_stats, w.chunk_part);
+                     w.cell_sumsq, w.cell_amax, w.tile_part, cell_stats, w.chunk_part);
   if ((e = hipGetLastError()) != hipSuccess || !box_stats) return e;
   hipLaunchKernelGGL(k_kdk_boxes, dim3((unsigned)nboxes), dim3(256), 0, s, boxes, w.chunk_part,
                      box_stats);

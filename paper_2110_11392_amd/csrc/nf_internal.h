@@ -174,8 +174,11 @@ __device__ __forceinline__ CellCoord cell_coord(float x, double cpl, int K) {
   r.ok = (t == t) && fabs(t) < kMaxCellCoord;  // false for NaN, +-inf, huge
   if (!r.ok) { r.c = 0; r.off = 0.0f; return r; }
   const double fl = floor(t);
-  int c = (int)fl % K;
-  if (c < 0) c += K;
+  int c = (int)fl;
+  if ((unsigned)c >= (unsigned)K) {  // outside [0, K): the periodic image (rare)
+    c %= K;
+    if (c < 0) c += K;
+  }
   r.c = c;
   r.off = (float)(t - (fl + 0.5));
   return r;
@@ -217,13 +220,12 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
 
 // kdk.hip
 constexpr int kKdkChunk = 512;   // cells per statistics chunk
-constexpr int kKdkTile = 1024;   // sorted slots per block of the update
+constexpr int kKdkTile = 512;   // sorted slots per block of the update
 struct KdkWork {
   double* cell_sumsq;   // cells_total: sum |v'|^2 per occupied cell
   double* cell_amax;    // cells_total: max |a| per occupied cell
   double* chunk_part;   // chunks x 3: min ratio, sum |v'|^2, max |a|
-  double* tile_part;    // tiles x 4: (sum, max) of the first and of the last run
-  int32_t* tile_cell;   // tiles x 2: cells of the first and of the last slot
+  double* tile_part;    // tiles x 4: (sum |v|^2, max |a|^2) of the first and of the last run
   int64_t chunks;
   int64_t tiles;
 };

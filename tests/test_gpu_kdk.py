@@ -114,7 +114,7 @@ def test_kdk_c2_deterministic_and_timestep(anf):
 
 
 def test_kdk_cells_cut_by_tiles(anf):
-    """Crowded cells spanning several 1024-slot tiles of the update (their
+    """Crowded cells spanning several 512-slot tiles of the update (their
     statistics are added from per-tile pieces), a cell that fills whole tiles,
     and particles stored in cell order (contiguous gathers)."""
     crowd = (np.array([0.3, 0.6, 0.55], np.float32) +

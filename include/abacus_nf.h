@@ -297,7 +297,7 @@ int abacus_nf_multipoles(const abacus_nf_box *boxes, int nboxes, const abacus_nf
 
 /* ---- kick, drift and the time step (Sec. 3.1, Eq. 1) --------------------- */
 
-/* Workspace bytes of abacus_nf_kick_drift (8 B x 2 per cell plus a little). */
+/* Workspace bytes of abacus_nf_kick_drift (32 B per particle, 16 B per cell, a little more). */
 int abacus_nf_kick_drift_workspace_bytes(const abacus_nf_box *boxes, int nboxes,
                                          size_t *bytes);
 

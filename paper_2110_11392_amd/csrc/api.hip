@@ -758,7 +758,7 @@ MpLayout mp_layout(const Resolved& r, int order, bool reduced) {
 }
 
 struct KdkLayout {
-  size_t boxtab, sumsq, amax, part, tile_part, total;
+  size_t boxtab, sumsq, amax, part, tile_part, mode, rec, total;
   int64_t tiles;
 };
 
@@ -776,6 +776,8 @@ KdkLayout kdk_layout(const Resolved& r) {
   L.part = take(sizeof(double) * 3 * (size_t)r.kdk_chunks);
   L.tiles = (r.n_total + kKdkTile - 1) / kKdkTile;
   L.tile_part = take(sizeof(double) * 4 * (size_t)L.tiles);
+  L.mode = take(sizeof(int32_t));
+  L.rec = take(sizeof(KdkRec) * (size_t)r.n_total);
   L.total = o;
   return L;
 }
@@ -896,6 +898,8 @@ int abacus_nf_kick_drift(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   w.cell_amax = at<double>(ws, L.amax);
   w.chunk_part = at<double>(ws, L.part);
   w.tile_part = at<double>(ws, L.tile_part);
+  w.mode = at<int32_t>(ws, L.mode);
+  w.rec = at<KdkRec>(ws, L.rec);
   w.chunks = r.kdk_chunks;
   w.tiles = L.tiles;
   Timer t(5, s);

@@ -10,20 +10,25 @@
 //
 // How it maps to CDNA4: the step is HBM-bound (64 bytes per particle), so what
 // matters is that every wave keeps many independent loads in flight.  The
-// update is flat over the sorted slots: a block owns a tile of kKdkTile
-// consecutive slots, each thread kKdkPer of them at a stride of the block size
-// (consecutive lanes, consecutive slots), with all of its gathers through the
-// permutation issued before any arithmetic.  Small tiles keep the block's
-// registers and LDS low, so that many blocks per CU have loads in flight
-// while others reduce.  Cells are runs of consecutive
+// update runs one of two ways, chosen on the device from a sample of the
+// permutation.  Particles kept in cell order (as the slabs of the paper's code
+// keep them): the update is flat over the sorted slots, a block owning a tile
+// of kKdkTile consecutive slots, each thread kKdkPer of them at a stride of
+// the block size, with all of its gathers through the permutation (contiguous
+// here) issued before any arithmetic.  Particles in any other order: a first
+// pass updates them in their own order, with coalesced loads and stores, and
+// leaves one 32-byte record per particle (cell, |v'|^2, |a|^2); the tile
+// kernel then gathers one record per slot instead of three 12-byte state
+// records from three random lines.  Small tiles keep the block's registers
+// and LDS low, so that many blocks per CU have loads in flight while others
+// reduce.  Cells are runs of consecutive
 // slots; a slot's cell is recomputed from its position before the drift with
 // the binning's own rule.  The per-cell statistics are a segmented reduction
 // in a fixed order: inside the tile each run is summed by one wave (lanes
 // strided over the run, then a fixed DPP tree), and a run cut by tile
 // boundaries leaves its pieces' partials per tile, which the statistics pass
 // adds in tile order afterwards.  No atomics, so every result is run-to-run
-// identical.  When the caller keeps particles in cell order (as the slabs of
-// the paper's code do) the gathers are contiguous.  The per-box statistics
+// identical, whichever way the update ran.  The per-box statistics
 // are a two-level, fixed-order reduction over chunks of 512 cells.
 #include "nf_internal.h"
 
@@ -86,12 +91,113 @@ __device__ __forceinline__ void write_cell(int64_t c, int64_t n, double s2, doub
   }
 }
 
+// One particle: the kick, the drift and its wrap (stored in place), and what
+// the statistics need of it: its cell in the binning (from the position before
+// the drift), |v'|^2 and |a|^2 (the square root is monotonic, so a cell's max
+// |a| is the root of its max |a|^2, taken once per cell).
+__device__ __forceinline__ void update_one(const DevBox& B, int64_t i, float px, float py,
+                                           float pz, float vx, float vy, float vz, float ax,
+                                           float ay, float az, float* __restrict__ pos,
+                                           float* __restrict__ vel, int& cell, double& v2,
+                                           double& a2) {
+  const double kick = B.kick, drift = B.drift, L = B.box_len, cpl = B.cells_per_len;
+  const int K = B.K;
+  const CellCoord cx = cell_coord(px, cpl, K), cy = cell_coord(py, cpl, K),
+                  cz = cell_coord(pz, cpl, K);
+  cell = B.cell_base + (cx.c * K + cy.c) * K + cz.c;
+  const float nvx = (float)((double)vx + kick * (double)ax);
+  const float nvy = (float)((double)vy + kick * (double)ay);
+  const float nvz = (float)((double)vz + kick * (double)az);
+  vel[3 * i] = nvx;
+  vel[3 * i + 1] = nvy;
+  vel[3 * i + 2] = nvz;
+  pos[3 * i] = wrap_coord((double)px + drift * (double)nvx, L);
+  pos[3 * i + 1] = wrap_coord((double)py + drift * (double)nvy, L);
+  pos[3 * i + 2] = wrap_coord((double)pz + drift * (double)nvz, L);
+  v2 = ((double)nvx * (double)nvx + (double)nvy * (double)nvy) + (double)nvz * (double)nvz;
+  a2 = ((double)ax * (double)ax + (double)ay * (double)ay) + (double)az * (double)az;
+}
+
+// Which way the update runs, chosen on the device from the permutation: when
+// most of kKdkThreads sampled neighbouring slots hold consecutive particles
+// (particles kept in cell order), the tile kernel updates each slot's particle
+// itself; else the particles are updated in their own order (coalesced) and
+// each leaves a record that the tile kernel gathers through the permutation
+// (one 32-byte record per slot instead of three 12-byte ones from three
+// random lines).  Both ways give the same bits.  Every block of the update
+// kernel takes the same samples and so the same decision; the tile kernel
+// reads it from `mode`.
+constexpr int kKdkSorted = 0, kKdkGather = 1;
+
+__device__ __forceinline__ int kdk_way(const int32_t* __restrict__ perm, int64_t n_total) {
+  const int64_t pairs = n_total > 1 ? n_total - 1 : 0;
+  const int samples = pairs < kKdkThreads ? (int)pairs : kKdkThreads;
+  const int64_t stride = samples > 0 ? pairs / samples : 0;  // k stride < pairs for k < samples
+  const int64_t at = (int64_t)threadIdx.x * stride;
+  const bool run = (int)threadIdx.x < samples && perm[at + 1] == perm[at] + 1;
+  const int runs = __syncthreads_count(run);
+  return 2 * runs >= samples ? kKdkSorted : kKdkGather;
+}
+
+// The gather way's update: particles in their own order, kKdkPer per thread
+// at a stride of the block size, persistent blocks over chunks of kKdkTile.
+__global__ __launch_bounds__(kKdkThreads) void k_kdk_update(
+    const DevBox* __restrict__ boxes, int nboxes, int64_t n_total,
+    const int32_t* __restrict__ perm, int32_t* __restrict__ mode, float* __restrict__ pos,
+    float* __restrict__ vel, const float* __restrict__ acc, KdkRec* __restrict__ rec) {
+  const int way = kdk_way(perm, n_total);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *mode = way;
+  if (way != kKdkGather) return;
+  __shared__ int s_box[2];
+  const int t = threadIdx.x;
+  const int64_t chunks = (n_total + kKdkTile - 1) / kKdkTile;
+  for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+    const int64_t c0 = ch * kKdkTile;
+    const int len = n_total - c0 < kKdkTile ? (int)(n_total - c0) : kKdkTile;
+    __syncthreads();  // the previous chunk's box range has been read
+    if (t == 0) {
+      s_box[0] = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, c0);
+      s_box[1] = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, c0 + len - 1);
+    }
+    __syncthreads();
+    const int box_lo = s_box[0], box_hi = s_box[1];
+    float ax[kKdkPer], ay[kKdkPer], az[kKdkPer], vx[kKdkPer], vy[kKdkPer], vz[kKdkPer];
+    float px[kKdkPer], py[kKdkPer], pz[kKdkPer];
+#pragma unroll
+    for (int k = 0; k < kKdkPer; ++k) {
+      const int j = k * kKdkThreads + t;
+      const int64_t i = c0 + (j < len ? j : 0);
+      ax[k] = acc[3 * i]; ay[k] = acc[3 * i + 1]; az[k] = acc[3 * i + 2];
+      vx[k] = vel[3 * i]; vy[k] = vel[3 * i + 1]; vz[k] = vel[3 * i + 2];
+      px[k] = pos[3 * i]; py[k] = pos[3 * i + 1]; pz[k] = pos[3 * i + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < kKdkPer; ++k) {
+      const int j = k * kKdkThreads + t;
+      if (j >= len) continue;
+      const int64_t i = c0 + j;
+      const int b = box_lo == box_hi ? box_lo : find_box_by_first(boxes, nboxes, i);
+      int cell;
+      double v2, a2;
+      update_one(boxes[b], i, px[k], py[k], pz[k], vx[k], vy[k], vz[k], ax[k], ay[k], az[k], pos,
+                 vel, cell, v2, a2);
+      KdkRec r;
+      r.v2 = v2;
+      r.a2 = a2;
+      r.cell = cell;
+      r.pad[0] = r.pad[1] = r.pad[2] = 0;
+      rec[i] = r;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
     const DevBox* __restrict__ boxes, int nboxes, int64_t n_total,
     const int32_t* __restrict__ off, const int32_t* __restrict__ perm, float* __restrict__ pos,
     float* __restrict__ vel, const float* __restrict__ acc, double* __restrict__ cell_sumsq,
     double* __restrict__ cell_amax, double* __restrict__ cell_stats,
-    double* __restrict__ tile_part) {
+    double* __restrict__ tile_part, const int32_t* __restrict__ mode,
+    const KdkRec* __restrict__ rec) {
   __shared__ double s_v2[kKdkTile], s_am[kKdkTile];
   __shared__ int s_cell[kKdkTile];
   __shared__ int s_run[kKdkTile + 1];
@@ -109,56 +215,61 @@ __global__ __launch_bounds__(kKdkThreads) void k_kick_drift(
   __syncthreads();
   const int box_lo = s_box[0], box_hi = s_box[1];
 
-  // ---- the update: every gather first, then the arithmetic ---------------
+  // ---- each slot's cell, |v'|^2 and |a|^2 -----------------------------------
+  // Either the update of the slot's particle (every gather first, then the
+  // arithmetic) or, when the particles were updated in their own order, the
+  // record the particle left.
   int64_t idx[kKdkPer];
 #pragma unroll
   for (int k = 0; k < kKdkPer; ++k) {
     const int j = k * kKdkThreads + t;
-    idx[k] = j < len ? (int64_t)perm[tile0 + j] : -1;
+    idx[k] = j < len ? (int64_t)perm[tile0 + j] : 0;
   }
-  float ax[kKdkPer], ay[kKdkPer], az[kKdkPer], vx[kKdkPer], vy[kKdkPer], vz[kKdkPer];
-  float px[kKdkPer], py[kKdkPer], pz[kKdkPer];
+  int cell[kKdkPer];
+  if (*mode == kKdkGather) {
+    KdkRec r[kKdkPer];
 #pragma unroll
-  for (int k = 0; k < kKdkPer; ++k) {
-    const int64_t i = idx[k] < 0 ? 0 : idx[k];
-    ax[k] = acc[3 * i]; ay[k] = acc[3 * i + 1]; az[k] = acc[3 * i + 2];
-    vx[k] = vel[3 * i]; vy[k] = vel[3 * i + 1]; vz[k] = vel[3 * i + 2];
-    px[k] = pos[3 * i]; py[k] = pos[3 * i + 1]; pz[k] = pos[3 * i + 2];
+    for (int k = 0; k < kKdkPer; ++k) r[k] = rec[idx[k]];
+#pragma unroll
+    for (int k = 0; k < kKdkPer; ++k) {
+      const int j = k * kKdkThreads + t;
+      cell[k] = r[k].cell;
+      s_cell[j] = r[k].cell;
+      s_v2[j] = r[k].v2;
+      s_am[j] = r[k].a2;
+    }
+  } else {
+    float ax[kKdkPer], ay[kKdkPer], az[kKdkPer], vx[kKdkPer], vy[kKdkPer], vz[kKdkPer];
+    float px[kKdkPer], py[kKdkPer], pz[kKdkPer];
+#pragma unroll
+    for (int k = 0; k < kKdkPer; ++k) {
+      const int64_t i = idx[k];
+      ax[k] = acc[3 * i]; ay[k] = acc[3 * i + 1]; az[k] = acc[3 * i + 2];
+      vx[k] = vel[3 * i]; vy[k] = vel[3 * i + 1]; vz[k] = vel[3 * i + 2];
+      px[k] = pos[3 * i]; py[k] = pos[3 * i + 1]; pz[k] = pos[3 * i + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < kKdkPer; ++k) {
+      const int j = k * kKdkThreads + t;
+      cell[k] = 0;
+      if (j >= len) continue;
+      const int b = box_lo == box_hi ? box_lo : find_box_by_first(boxes, nboxes, tile0 + j);
+      double v2, a2;
+      update_one(boxes[b], idx[k], px[k], py[k], pz[k], vx[k], vy[k], vz[k], ax[k], ay[k], az[k],
+                 pos, vel, cell[k], v2, a2);
+      s_cell[j] = cell[k];
+      s_v2[j] = v2;
+      s_am[j] = a2;
+    }
   }
+  // Only the tile's first and last runs can belong to cells that continue
+  // past the tile: the begin of the first slot's cell and the end of the last
+  // slot's cell tell.
 #pragma unroll
   for (int k = 0; k < kKdkPer; ++k) {
     const int j = k * kKdkThreads + t;
-    if (j >= len) continue;
-    const bool edge_first = j == 0, edge_last = j == len - 1;
-    const int64_t i = idx[k];
-    const int b = box_lo == box_hi ? box_lo : find_box_by_first(boxes, nboxes, tile0 + j);
-    const DevBox& B = boxes[b];
-    const double kick = B.kick, drift = B.drift, L = B.box_len, cpl = B.cells_per_len;
-    const int K = B.K;
-    // the slot's cell: the binning's rule on the position before the drift
-    const CellCoord cx = cell_coord(px[k], cpl, K), cy = cell_coord(py[k], cpl, K),
-                    cz = cell_coord(pz[k], cpl, K);
-    const int cj = B.cell_base + (cx.c * K + cy.c) * K + cz.c;
-    s_cell[j] = cj;
-    // only the tile's first and last runs can belong to cells that continue
-    // past the tile: the begin of the first slot's cell and the end of the
-    // last slot's cell tell
-    if (edge_first) s_edge[0] = off[cj];
-    if (edge_last) s_edge[1] = off[cj + 1];
-    const float nvx = (float)((double)vx[k] + kick * (double)ax[k]);
-    const float nvy = (float)((double)vy[k] + kick * (double)ay[k]);
-    const float nvz = (float)((double)vz[k] + kick * (double)az[k]);
-    vel[3 * i] = nvx;
-    vel[3 * i + 1] = nvy;
-    vel[3 * i + 2] = nvz;
-    pos[3 * i] = wrap_coord((double)px[k] + drift * (double)nvx, L);
-    pos[3 * i + 1] = wrap_coord((double)py[k] + drift * (double)nvy, L);
-    pos[3 * i + 2] = wrap_coord((double)pz[k] + drift * (double)nvz, L);
-    s_v2[j] = ((double)nvx * (double)nvx + (double)nvy * (double)nvy) + (double)nvz * (double)nvz;
-    // |a|^2: the square root is monotonic, so the cell's max |a| is the root
-    // of its max |a|^2, taken once per cell
-    s_am[j] =
-        ((double)ax[k] * (double)ax[k] + (double)ay[k] * (double)ay[k]) + (double)az[k] * (double)az[k];
+    if (j == 0) s_edge[0] = off[cell[k]];
+    if (j == len - 1) s_edge[1] = off[cell[k] + 1];
   }
   __syncthreads();
 
@@ -337,9 +448,16 @@ hipError_t launch_kick_drift(const DevBox* boxes, int nboxes, int64_t n_total,
                              double* cell_stats, double* box_stats, hipStream_t s) {
   hipError_t e;
   if (w.tiles > 0) {
+    // the update kernel also decides the way (and idles, cheaply, in cell order)
+    const int upd_blocks =
+        persistent_blocks(reinterpret_cast<const void*>(&k_kdk_update), kKdkThreads) / 2;
+    const int64_t ub = w.tiles < upd_blocks ? w.tiles : upd_blocks;
+    hipLaunchKernelGGL(k_kdk_update, dim3((unsigned)(ub > 0 ? ub : 1)), dim3(kKdkThreads), 0, s,
+                       boxes, nboxes, n_total, perm, w.mode, pos, vel, acc, w.rec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)w.tiles), dim3(kKdkThreads), 0, s, boxes,
                        nboxes, n_total, off, perm, pos, vel, acc, w.cell_sumsq, w.cell_amax,
-                       cell_stats, w.tile_part);
+                       cell_stats, w.tile_part, w.mode, w.rec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (!cell_stats && !box_stats) return hipSuccess;

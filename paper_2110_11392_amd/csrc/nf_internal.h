@@ -221,11 +221,19 @@ hipError_t launch_multipoles(const DevBox* boxes, int nboxes, int64_t cells_tota
 // kdk.hip
 constexpr int kKdkChunk = 512;   // cells per statistics chunk
 constexpr int kKdkTile = 512;   // sorted slots per block of the update
+struct KdkRec {  // what one particle's update leaves for the statistics (32 bytes)
+  double v2, a2;  // |v'|^2 and |a|^2
+  int32_t cell;   // its cell in the binning
+  int32_t pad[3];
+};
+static_assert(sizeof(KdkRec) == 32, "one 32-byte record per particle");
 struct KdkWork {
   double* cell_sumsq;   // cells_total: sum |v'|^2 per occupied cell
   double* cell_amax;    // cells_total: max |a| per occupied cell
   double* chunk_part;   // chunks x 3: min ratio, sum |v'|^2, max |a|
   double* tile_part;    // tiles x 4: (sum |v|^2, max |a|^2) of the first and of the last run
+  int32_t* mode;        // 1: which way the update runs (chosen on the device)
+  KdkRec* rec;          // n_total: per-particle records of the gather way
   int64_t chunks;
   int64_t tiles;
 };

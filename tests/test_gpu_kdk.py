@@ -134,3 +134,36 @@ def test_kdk_cells_cut_by_tiles(anf):
     say("[kdk] C1 in cell order")
     run_case(anf, [synth.Box(np.ascontiguousarray(b.pos[perm]), b.box, b.cpd, b.radius,
                              b.eps_plummer)], 0.01, 0.02)
+
+
+def test_kdk_same_bits_in_either_particle_order(anf):
+    """The update runs one of two ways, chosen from the permutation: over the
+    sorted slots (particles kept in cell order) or over the particles in
+    their own order with per-particle records gathered afterwards.  The same
+    particles stored in a shuffled order and in cell order take the two ways;
+    every result must be bitwise the same, particle by particle and cell by
+    cell."""
+    b = synth.config("C5")[0]
+    rng = np.random.default_rng(77)
+    shuffled = rng.permutation(b.n)
+    pos_s = np.ascontiguousarray(b.pos[shuffled])
+    vel_h, acc_h = state([b], 500)
+    _, _, perm, _ = oracle.bin(pos_s, b.box, b.cpd)
+    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer)])
+    outs = []
+    for order in (np.arange(b.n), perm):
+        say(f"[kdk] C5 {'shuffled' if order is not perm else 'cell'} order")
+        pos = torch.from_numpy(np.ascontiguousarray(pos_s[order])).cuda()
+        vel = torch.from_numpy(np.ascontiguousarray(vel_h[order])).cuda()
+        acc = torch.from_numpy(np.ascontiguousarray(acc_h[order])).cuda()
+        bd = nf.bin(pos)
+        cs, bs = nf.kick_drift(bd, pos, vel, acc, 0.02, 0.01, cell_stats=True)
+        p, v = np.empty_like(pos_s), np.empty_like(vel_h)
+        p[order], v[order] = pos.cpu().numpy(), vel.cpu().numpy()
+        outs.append((p, v, cs.cpu().numpy(), bs.cpu().numpy()))
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    po, vo, cso, _ = oracle.kick_drift(pos_s, vel_h, acc_h, b.box, b.cpd, 0.02, 0.01)
+    assert np.array_equal(outs[0][0].view(np.uint32), po.view(np.uint32))
+    assert np.array_equal(outs[0][1].view(np.uint32), vo.view(np.uint32))
+    assert np.array_equal(outs[0][2][:, 1], cso[:, 1])

@@ -322,6 +322,10 @@ int abacus_nf_kick_drift_workspace_bytes(const abacus_nf_box *boxes, int nboxes,
  *   box_stats  NULL, or nboxes x 4 FP64: min over cells with n > 0 and
  *              a_max > 0 of v_rms/a_max (+inf if none), the box's global
  *              v_rms, global a_max and N -- the inputs of abacus_nf_timestep.
+ * The particles may be stored in any order; the call checks a sample of the
+ * permutation on the device and, unless they are mostly in the binning's cell
+ * order, updates them in their own order first (the same bits either way);
+ * storing them in cell order makes it fastest.
  * Results are run-to-run deterministic.  Errors: EINVAL for a bad box, a NULL
  * or non-finite factor, or NULL state arrays; EWORKSPACE as elsewhere.
  */

@@ -415,7 +415,7 @@ def main():
                     choices=["compensated", "chunked", "single"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle comparison of the timed outputs (and its timing)")
-    ap.add_argument("--accuracy-sinks", type=int, default=3000,
+    ap.add_argument("--accuracy-sinks", type=int, default=10000,
                     help="sinks of the oracle comparison, drawn in proportion to N_b")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of timing candidates")

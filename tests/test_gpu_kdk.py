@@ -136,6 +136,38 @@ def test_kdk_cells_cut_by_tiles(anf):
                              b.eps_plummer)], 0.01, 0.02)
 
 
+def shuffled_and_cell_order_runs(anf, boxes, kick, drift, seed):
+    """Run the kick-drift on the same particles stored shuffled (within each
+    box) and in the binning's cell order; return both results mapped back to
+    the shuffled order, with the shuffled inputs."""
+    rng = np.random.default_rng(seed)
+    pos_s, perm_all, first = [], [], 0
+    for b in boxes:
+        sh = rng.permutation(b.n)
+        p = np.ascontiguousarray(b.pos[sh])
+        pos_s.append(p)
+        if b.n:
+            _, _, perm, _ = oracle.bin(p, b.box, b.cpd)
+            perm_all.append(first + perm)
+        first += b.n
+    pos_s = np.ascontiguousarray(np.concatenate(pos_s))
+    cell_order = np.concatenate(perm_all)
+    vel_h, acc_h = state(boxes, seed + 1)
+    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer) for b in boxes])
+    outs = []
+    for label, order in (("shuffled", np.arange(pos_s.shape[0])), ("cell", cell_order)):
+        say(f"[kdk] {len(boxes)} box(es), {label} order")
+        pos = torch.from_numpy(np.ascontiguousarray(pos_s[order])).cuda()
+        vel = torch.from_numpy(np.ascontiguousarray(vel_h[order])).cuda()
+        acc = torch.from_numpy(np.ascontiguousarray(acc_h[order])).cuda()
+        bd = nf.bin(pos)
+        cs, bs = nf.kick_drift(bd, pos, vel, acc, kick, drift, cell_stats=True)
+        p, v = np.empty_like(pos_s), np.empty_like(vel_h)
+        p[order], v[order] = pos.cpu().numpy(), vel.cpu().numpy()
+        outs.append((p, v, cs.cpu().numpy(), bs.cpu().numpy()))
+    return outs, pos_s, vel_h, acc_h
+
+
 def test_kdk_same_bits_in_either_particle_order(anf):
     """The update runs one of two ways, chosen from the permutation: over the
     sorted slots (particles kept in cell order) or over the particles in
@@ -144,26 +176,25 @@ def test_kdk_same_bits_in_either_particle_order(anf):
     every result must be bitwise the same, particle by particle and cell by
     cell."""
     b = synth.config("C5")[0]
-    rng = np.random.default_rng(77)
-    shuffled = rng.permutation(b.n)
-    pos_s = np.ascontiguousarray(b.pos[shuffled])
-    vel_h, acc_h = state([b], 500)
-    _, _, perm, _ = oracle.bin(pos_s, b.box, b.cpd)
-    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer)])
-    outs = []
-    for order in (np.arange(b.n), perm):
-        say(f"[kdk] C5 {'shuffled' if order is not perm else 'cell'} order")
-        pos = torch.from_numpy(np.ascontiguousarray(pos_s[order])).cuda()
-        vel = torch.from_numpy(np.ascontiguousarray(vel_h[order])).cuda()
-        acc = torch.from_numpy(np.ascontiguousarray(acc_h[order])).cuda()
-        bd = nf.bin(pos)
-        cs, bs = nf.kick_drift(bd, pos, vel, acc, 0.02, 0.01, cell_stats=True)
-        p, v = np.empty_like(pos_s), np.empty_like(vel_h)
-        p[order], v[order] = pos.cpu().numpy(), vel.cpu().numpy()
-        outs.append((p, v, cs.cpu().numpy(), bs.cpu().numpy()))
+    outs, pos_s, vel_h, acc_h = shuffled_and_cell_order_runs(anf, [b], 0.02, 0.01, 77)
     for x, y in zip(*outs):
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
     po, vo, cso, _ = oracle.kick_drift(pos_s, vel_h, acc_h, b.box, b.cpd, 0.02, 0.01)
     assert np.array_equal(outs[0][0].view(np.uint32), po.view(np.uint32))
     assert np.array_equal(outs[0][1].view(np.uint32), vo.view(np.uint32))
     assert np.array_equal(outs[0][2][:, 1], cso[:, 1])
+
+
+def test_kdk_same_bits_in_either_order_ragged_batch(anf):
+    """The two ways on a ragged batch (an empty box, a one-particle box, a
+    sparse K = 70 box, per-box factors, a drift that wraps), including the
+    particles that a box's first and last tiles share with its neighbours."""
+    boxes = [synth.Box(synth.clustered(2500, 6, 8, 13), 1.0, 8, 2, 1 / 500),
+             synth.Box(np.zeros((0, 3), np.float32), 1.0, 5, 2, 1 / 500),
+             synth.Box(synth.uniform(1, 14), 2.0, 5, 2, 1 / 500),
+             synth.Box(synth.clustered(4100, 9, 70, 15), 1.0, 70, 2, 1 / 700),
+             synth.Box(synth.uniform(3000, 16, 3.7), 3.7, 11, 2, 3.7 / 640)]
+    kick, drift = [0.01, 0.02, -0.03, 0.5, 0.0], [0.02, 0.0, 1.5, -0.25, 0.125]
+    outs, _, _, _ = shuffled_and_cell_order_runs(anf, boxes, kick, drift, 91)
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))

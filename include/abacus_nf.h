@@ -198,6 +198,22 @@ int abacus_nf_forces_f64(const abacus_nf_box *boxes, int nboxes, const abacus_nf
                          double *acc, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * abacus_nf_forces_vjp_f64 -- the adjoint of abacus_nf_forces_f64, every
+ * operation after the stored FP32 cell offsets in FP64: for a cotangent w,
+ *   grad_k = sum_{j in NF(k)} [ f(r)(w_j - w_k) + (f'(r)/r)(d.(w_j - w_k)) d ]
+ * with d = x_j - x_k and f from Eq. 3 (Sec. 3.2) or, with ABACUS_NF_PLUMMER,
+ * Eq. 2; the binning is held fixed (the derivative on the piecewise-smooth
+ * branch), a plain FP64 sum per particle.
+ *   w      n_total x 3 FP64 cotangent in ORIGINAL particle order.
+ *   grad   n_total x 3 FP64 output in ORIGINAL particle order, box units.
+ *   flags  0 or ABACUS_NF_PLUMMER.  Same workspace as abacus_nf_forces.
+ * Errors as abacus_nf_forces_f64.  Results are run-to-run deterministic.
+ */
+int abacus_nf_forces_vjp_f64(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                             const double *w, double *grad, uint32_t flags, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/*
  * abacus_nf_forces_vjp -- vector-Jacobian product of the accelerations.
  * For a cotangent w (n_total x 3 FP32, original order) returns
  *   grad_k = d/dx_k sum_i w_i . a_i

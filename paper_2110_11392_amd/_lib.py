@@ -65,7 +65,7 @@ EXPORTS = ("abacus_nf_layout", "abacus_nf_workspace_bytes", "abacus_nf_bin", "ab
            "abacus_nf_timing_read", "abacus_nf_timing_reset", "abacus_nf_multipole_terms",
            "abacus_nf_multipoles_workspace_bytes", "abacus_nf_multipoles",
            "abacus_nf_kick_drift_workspace_bytes", "abacus_nf_kick_drift", "abacus_nf_timestep",
-           "abacus_nf_forces_f64", "abacus_nf_forces_noalloc")
+           "abacus_nf_forces_f64", "abacus_nf_forces_vjp_f64", "abacus_nf_forces_noalloc")
 
 _lib = None
 
@@ -95,6 +95,8 @@ def load() -> ctypes.CDLL:
     lib.abacus_nf_forces.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, vp, u32, vp, sz, vp]
     lib.abacus_nf_forces_vjp.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, u32, vp, sz, vp]
     lib.abacus_nf_forces_f64.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp]
+    lib.abacus_nf_forces_vjp_f64.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, u32, vp, sz,
+                                             vp]
     lib.abacus_nf_forces_noalloc.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, vp, u32, vp]
     TuneP = ctypes.POINTER(Tuning)
     lib.abacus_nf_autotune.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp, TuneP,

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libabacus_nf.so")
 ARCH = "gfx950"
 
-SOURCES = ["common.hip", "bin.hip", "plan.hip", "pairs.hip", "pairs64.hip", "vjp.hip", "reduce.hip",
+SOURCES = ["common.hip", "bin.hip", "plan.hip", "pairs.hip", "pairs64.hip", "vjp.hip", "vjp64.hip",
+           "reduce.hip",
            "tune.hip",
            "multipoles.hip", "kdk.hip", "api.hip"]
 

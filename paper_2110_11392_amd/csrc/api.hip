@@ -538,6 +538,37 @@ int abacus_nf_forces_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   return ABACUS_NF_OK;
 }
 
+int abacus_nf_forces_vjp_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                             const double* wv, double* grad, uint32_t flags, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (flags & ~ABACUS_NF_PLUMMER) return ABACUS_NF_EINVAL;
+  Resolved r;
+  int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
+  if (rc) return rc;
+  if (!binned_ok(b, r.n_total) || (r.n_total > 0 && (!wv || !grad))) return ABACUS_NF_EINVAL;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBox* dboxes = at<DevBox>(ws, L.boxtab);
+  ANF_HIP(write_box_table(r.boxes.data(), nboxes, dboxes, s), "box table");
+  PlanWork w = plan_work(ws, L);
+  // Like the FP64 forward kernel: whole items only, in the default span.
+  KernelConfig cfg = default_config(1);
+  cfg.split = 0;
+  w.split_items = 0;
+  ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, 1, w, s),
+          "work plan");
+  if (r.n_total > 0) {
+    Timer t(1, s);
+    // the sorted FP64 cotangents take the adjoint's 24-byte source-record region
+    ANF_HIP(launch_vjp_f64(dboxes, w, b->cell_offsets, b->rel, b->perm, wv,
+                           at<double>(ws, L.src_w), r.n_total, grad, s),
+            "FP64 adjoint pair kernel");
+    t.done();
+  }
+  return ABACUS_NF_OK;
+}
+
 int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
                          const float* wv, float* grad, uint32_t flags, void* ws, size_t ws_bytes,
                          void* stream) {

@@ -370,6 +370,11 @@ void clear_config(const TuneKey& k);
 hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int32_t* off,
                               const float* rel, const int32_t* perm, double* acc, float* src3,
                               int64_t n_total, hipStream_t s);
+// vjp64.hip: the FP64 adjoint (whole tasks only); w64 is workspace for n_total x 3
+// FP64 cotangents in sorted order.
+hipError_t launch_vjp_f64(const DevBox* boxes, const PlanWork& w, const int32_t* off,
+                          const float* rel, const int32_t* perm, const double* wvec,
+                          double* w64, int64_t n_total, double* grad, hipStream_t s);
 hipError_t launch_forward(AccMode mode, bool count_pairs, const KernelConfig& cfg,
                           const DevBox* boxes, const PlanWork& w, int64_t pencils_total,
                           const int32_t* cell_offsets, const float* rel, const int32_t* perm,

@@ -177,6 +177,26 @@ class NearField:
                    "abacus_nf_forces_f64")
         return acc
 
+    def forces_vjp_f64(self, binned: Binned, w: torch.Tensor,
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Adjoint of forces_f64 for an FP64 cotangent w (n, 3), original order:
+        the FP64 adjoint pair kernel.  Returns (n, 3) FP64."""
+        if w.dtype != torch.float64 or tuple(w.shape) != (self.n_total, 3) or \
+                not w.is_contiguous() or w.device != self.device:
+            raise ValueError("w must be a contiguous (n, 3) float64 tensor on the device")
+        grad = out if out is not None else torch.empty((self.n_total, 3), dtype=torch.float64,
+                                                       device=self.device)
+        if grad.dtype != torch.float64 or tuple(grad.shape) != (self.n_total, 3) or \
+                not grad.is_contiguous():
+            raise ValueError("out must be a contiguous (n, 3) float64 tensor")
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_forces_vjp_f64(self._boxes, self.nboxes, ctypes.byref(cs),
+                                                      _ptr(w), _ptr(grad), LAWS[self.law],
+                                                      _ptr(self.workspace), self.workspace_bytes,
+                                                      _stream()),
+                   "abacus_nf_forces_vjp_f64")
+        return grad
+
     def forces_vjp(self, binned: Binned, w: torch.Tensor, accumulation: str = "compensated",
                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if w.dtype != torch.float32 or tuple(w.shape) != (self.n_total, 3) or not w.is_contiguous():

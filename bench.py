@@ -261,7 +261,7 @@ class Stepper:
 def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
     """The widened rows, each timed by the library's own HIP events over `reps`
     launches outside the main step: the density estimate fused into the
-    forward kernel, the Plummer law, the FP64 pair kernel, the cell multipoles
+    forward kernel, the Plummer law, the FP64 pair kernels, the cell multipoles
     (p = 8, complete and reduced) and the kick-drift step.  Returns per-row
     figures."""
     import numpy as np
@@ -303,7 +303,12 @@ def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
     acc64 = torch.empty((nf.n_total, 3), dtype=torch.float64, device=dev)
     f64 = kernel_ms(0, lambda: nf.forces_f64(st.binned, out=acc64))
     rows["fp64_forward"] = {"forward_ms": f64, "vs_fp32": f64 / fwd}
-    del acc64
+    # and its adjoint, against the FP32 adjoint of the main step's shapes
+    w64 = st.wvec.to(torch.float64)
+    adj = kernel_ms(1, lambda: nf.forces_vjp(st.binned, st.wvec, accumulation, out=st.acc))
+    a64 = kernel_ms(1, lambda: nf.forces_vjp_f64(st.binned, w64, out=acc64))
+    rows["fp64_adjoint"] = {"adjoint_ms": a64, "vs_fp32": a64 / adj}
+    del acc64, w64
     # multipoles, p = 8
     n, cells = nf.n_total, nf.cells_total
     out_c = torch.empty((cells, 165), dtype=torch.float64, device=dev)

@@ -328,21 +328,52 @@ class _NearFieldFn(torch.autograd.Function):
         return g, None, None
 
 
+class _NearFieldF64Fn(torch.autograd.Function):
+    """The FP64 kernels: acc (FP64) = near-field accelerations of pos; backward
+    is the FP64 adjoint kernel on the saved binning, the gradient returned in
+    the dtype of pos."""
+
+    @staticmethod
+    def forward(ctx, pos, nf: NearField):
+        binned = nf.bin(pos.contiguous())
+        acc = nf.forces_f64(binned)
+        ctx.nf = nf
+        ctx.binned = binned
+        ctx.pos_dtype = pos.dtype
+        return acc
+
+    @staticmethod
+    def backward(ctx, grad_acc):
+        g = ctx.nf.forces_vjp_f64(ctx.binned, grad_acc.contiguous().double())
+        return g.to(ctx.pos_dtype), None
+
+
+PRECISIONS = ("fp32", "fp64")
+
+
 def near_field(pos: torch.Tensor, box: float, cpd: int, radius: int, eps_plummer: float,
                accumulation: str = "compensated", nf: Optional[NearField] = None,
-               law: str = "spline") -> torch.Tensor:
-    """Near-field accelerations of one periodic box, differentiable in ``pos``.
+               law: str = "spline", precision: str = "fp32") -> torch.Tensor:
+    """Near-field accelerations of one periodic box, differentiable in ``pos``
+    (FP32 positions; the binning is held fixed under differentiation).
 
-    ``accumulation`` is how each sink's FP32 sum is formed, in the forward and
-    the adjoint alike: "single" (one running FP32 accumulator, as the paper's
-    kernel), "chunked" (FP32 partials over at most 64 sources added to it) or
-    "compensated" (those partials folded into an FP32 sum and error term)."""
+    ``precision`` "fp32" runs the FP32 kernels, and ``accumulation`` is how each
+    sink's FP32 sum is formed, in the forward and the adjoint alike: "single"
+    (one running FP32 accumulator, as the paper's kernel), "chunked" (FP32
+    partials over at most 64 sources added to it) or "compensated" (those
+    partials folded into an FP32 sum and error term).  "fp64" runs the FP64
+    kernels (plain FP64 sums; ``accumulation`` does not apply) and returns FP64
+    accelerations."""
+    if precision not in PRECISIONS:
+        raise ValueError(f"unknown precision {precision!r}; one of {list(PRECISIONS)}")
     if accumulation not in ACCUMULATION:
         raise ValueError(f"unknown accumulation {accumulation!r}; "
                          f"one of {sorted(ACCUMULATION)}")
     if nf is None:
         nf = NearField([BoxSpec(pos.shape[0], box, cpd, radius, eps_plummer)], device=pos.device,
                        law=law)
+    if precision == "fp64":
+        return _NearFieldF64Fn.apply(pos, nf)
     return _NearFieldFn.apply(pos, nf, accumulation)
 
 

@@ -195,3 +195,26 @@ def test_fp64_adjoint_on_c5_within_the_offset_rounding(anf, law):
     d = np.linalg.norm(g64 - g32) / np.linalg.norm(g64)
     say(f"  relative 2-norm fp64 {e64:.3g}, fp32 {e32:.3g}; fp64 vs fp32 {d:.3g}")
     assert e64 <= VJP_TOL and e64 <= 1.1 * e32 and d <= 1e-5
+
+
+def test_fp64_autograd_equals_the_kernels(anf):
+    """near_field(..., precision="fp64"): the forward is the FP64 kernel and the
+    backward the FP64 adjoint on the same binning, bit for bit; an unknown
+    precision is refused."""
+    pos, K, R, eps = case_spec("clustered_K8")
+    n = pos.shape[0]
+    w32 = synth.gaussian_weights(n, 602)
+    nf = anf.NearField([anf.BoxSpec(n, 1.0, K, R, eps)])
+    p = torch.from_numpy(pos).cuda().requires_grad_(True)
+    acc = anf.near_field(p, 1.0, K, R, eps, nf=nf, precision="fp64")
+    assert acc.dtype == torch.float64
+    w64 = torch.from_numpy(w32.astype(np.float64)).cuda()
+    (acc * w64).sum().backward()
+    bd = nf.bin(torch.from_numpy(pos).cuda())
+    ref_a = nf.forces_f64(bd)
+    ref_g = nf.forces_vjp_f64(bd, w64)
+    assert torch.equal(acc.detach(), ref_a)
+    assert p.grad.dtype == torch.float32
+    assert torch.equal(p.grad, ref_g.float())
+    with pytest.raises(ValueError):
+        anf.near_field(p, 1.0, K, R, eps, nf=nf, precision="fp16")

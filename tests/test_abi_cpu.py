@@ -274,6 +274,27 @@ def test_fp64_forces_arguments_without_gpu():
                                     None) == _lib.EWORKSPACE
 
 
+def test_fp64_adjoint_arguments_without_gpu():
+    """The FP64 adjoint takes only the Plummer flag, needs the cotangent, the
+    output and the workspace, and rejects a bad box, before any HIP call."""
+    lib = _lib.load()
+    b = boxes((100, 1.0, 8, 2, 1e-3))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.abacus_nf_workspace_bytes(b, 1, ctypes.byref(nbytes)) == 0
+    fake = ctypes.c_void_p(0x1000)
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+    for flags in (_lib.COMPENSATED, _lib.SINGLE_ACC, _lib.COUNT_PAIRS, 0x80):
+        assert lib.abacus_nf_forces_vjp_f64(b, 1, ctypes.byref(binned), fake, fake, flags, fake,
+                                            nbytes, None) == _lib.EINVAL
+    for w, g in ((None, fake), (fake, None)):
+        assert lib.abacus_nf_forces_vjp_f64(b, 1, ctypes.byref(binned), w, g, 0, fake, nbytes,
+                                            None) == _lib.EINVAL
+    assert lib.abacus_nf_forces_vjp_f64(boxes((100, 1.0, 4, 2, 1e-3)), 1, ctypes.byref(binned),
+                                        fake, fake, 0, fake, nbytes, None) == _lib.EINVAL
+    assert lib.abacus_nf_forces_vjp_f64(b, 1, ctypes.byref(binned), fake, fake, _lib.PLUMMER,
+                                        None, nbytes, None) == _lib.EWORKSPACE
+
+
 def test_noalloc_forces_arguments_without_gpu():
     """The no-allocation entry point validates like abacus_nf_forces and refuses
     a problem its static scratch cannot hold, all before any HIP call."""

@@ -531,7 +531,7 @@ int abacus_nf_forces_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   if (r.n_total > 0) {
     Timer t(0, s);
     ANF_HIP(launch_forward_f64(dboxes, w, b->cell_offsets, b->rel, b->perm, acc,
-                               at<float>(ws, L.src_w), r.n_total, s),
+                               at<double>(ws, L.src_w), r.n_total, s),
             "FP64 forward pair kernel");
     t.done();
   }

@@ -366,9 +366,10 @@ void clear_config(const TuneKey& k);
 
 // pairs.hip
 // src3: workspace for n_total packed (x, y, z) source records.
-// pairs64.hip: the FP64 forward kernel (whole tasks only: plan it with no splits)
+// pairs64.hip: the FP64 forward kernel (whole tasks only: plan it with no splits);
+// src3: workspace for n_total (x, y, z) FP64 source records (the 24-byte region)
 hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int32_t* off,
-                              const float* rel, const int32_t* perm, double* acc, float* src3,
+                              const float* rel, const int32_t* perm, double* acc, double* src3,
                               int64_t n_total, hipStream_t s);
 // vjp64.hip: the FP64 adjoint (whole tasks only); w64 is workspace for n_total x 3
 // FP64 cotangents in sorted order.

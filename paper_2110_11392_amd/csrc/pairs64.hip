@@ -9,9 +9,10 @@
 // near field of the stored positions to FP64 rounding.
 //
 // How it maps to CDNA4: the FP32 kernel's work items, task queue and wave
-// structure, with sources still broadcast through SGPRs as packed FP32
-// records and widened per pair; MI355X issues FP64 FMAs at the FP32
-// (non-packed) rate, so the cost is the longer reciprocal square root.
+// structure, with sources still broadcast through SGPRs, as packed records of
+// the FP32 offsets widened to FP64 once per call (exact), so no pair converts
+// them; MI355X issues FP64 FMAs at the FP32 (non-packed) rate, so the cost is
+// the longer reciprocal square root.
 #include "nf_internal.h"
 
 namespace anf {
@@ -40,12 +41,12 @@ struct Const64 {
 };
 
 template <bool kNear>
-__device__ __forceinline__ void interact64(float sx, float sy, float sz, double qx, double qy,
+__device__ __forceinline__ void interact64(double sx, double sy, double sz, double qx, double qy,
                                            double qz, const Const64& k, double& tx, double& ty,
                                            double& tz) {
-  const double dx = (double)sx - qx;
-  const double dy = (double)sy - qy;
-  const double dz = (double)sz - qz;
+  const double dx = sx - qx;
+  const double dy = sy - qy;
+  const double dz = sz - qz;
   const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, k.g)));
   const double rinv = rsqrt64(r2);
   const double rinv3 = (rinv * rinv) * rinv;
@@ -61,12 +62,12 @@ __device__ __forceinline__ void interact64(float sx, float sy, float sz, double 
 }
 
 template <bool kNear>
-__device__ __forceinline__ void sum64(const float* __restrict__ src3, int beg, int end, double qx,
-                                      double qy, double qz, const Const64& k, double& tx,
-                                      double& ty, double& tz) {
+__device__ __forceinline__ void sum64(const double* __restrict__ src3, int beg, int end,
+                                      double qx, double qy, double qz, const Const64& k,
+                                      double& tx, double& ty, double& tz) {
   int j = beg;
   for (; j + 2 <= end; j += 2) {
-    float c[6];
+    double c[6];
 #pragma unroll
     for (int u = 0; u < 6; ++u) c[u] = src3[3 * j + u];
     interact64<kNear>(c[0], c[1], c[2], qx, qy, qz, k, tx, ty, tz);
@@ -79,16 +80,16 @@ __device__ __forceinline__ void sum64(const float* __restrict__ src3, int beg, i
 // The two far edge cells of a two-cell item walked together (the forward FP32
 // kernel's scheme): per chunk of kChunk positions the wave stages both runs in
 // its own LDS slot, then each lane sums its own run's records from there.
-__device__ __forceinline__ void sum64_edge_runs(const float* __restrict__ src3,
-                                                float* __restrict__ slot, int lane, bool upper,
+__device__ __forceinline__ void sum64_edge_runs(const double* __restrict__ src3,
+                                                double* __restrict__ slot, int lane, bool upper,
                                                 int bl, int nl, int bh, int nh, double qx,
                                                 double qy, double qz, const Const64& k,
                                                 double& tx, double& ty, double& tz) {
   const int nmax = nl > nh ? nl : nh;
   const int rn = upper ? nh : nl;
-  const float* mine = slot + (upper ? 3 * kChunk : 0);
-  const float* __restrict__ runl = src3 + 3 * (int64_t)bl;
-  const float* __restrict__ runh = src3 + 3 * (int64_t)bh;
+  const double* mine = slot + (upper ? 3 * kChunk : 0);
+  const double* __restrict__ runl = src3 + 3 * (int64_t)bl;
+  const double* __restrict__ runh = src3 + 3 * (int64_t)bh;
   for (int cb = 0; cb < nmax; cb += kChunk) {
     const int ce = cb + kChunk < nmax ? cb + kChunk : nmax;
     if (cb + lane < nl) {
@@ -114,11 +115,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const int32_t* __restrict__ tasks, const int32_t* __restrict__ item_cost,
     int32_t* __restrict__ ctrl,
     const int32_t* __restrict__ off, const float4* __restrict__ rel,
-    const float* __restrict__ src3, const int32_t* __restrict__ perm,
+    const double* __restrict__ src3, const int32_t* __restrict__ perm,
     double* __restrict__ acc_out, int n_static) {
   const int lane = threadIdx.x & 63;
-  __shared__ float edge_lds[4][2 * kChunk * 3];  // per wave: two staged runs
-  float* const edge_slot = edge_lds[threadIdx.x >> 6];
+  __shared__ double edge_lds[4][2 * kChunk * 3];  // per wave: two staged runs
+  double* const edge_slot = edge_lds[threadIdx.x >> 6];
   const int n_tasks = uni64(ctrl[kCtrlNTasks]);
   bool first = true;
   while (true) {
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 __global__ __launch_bounds__(256) void k_pack_sources64(const float4* __restrict__ rel, int64_t n,
-                                                        float* __restrict__ src3) {
+                                                        double* __restrict__ src3) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const float4 r = rel[s];
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(256) void k_pack_sources64(const float4* __restrict
 }
 
 hipError_t launch_forward_f64(const DevBox* boxes, const PlanWork& w, const int32_t* off,
-                              const float* rel, const int32_t* perm, double* acc, float* src3,
+                              const float* rel, const int32_t* perm, double* acc, double* src3,
                               int64_t n_total, hipStream_t s) {
   if (n_total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack_sources64, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s,

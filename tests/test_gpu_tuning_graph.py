@@ -147,16 +147,24 @@ def test_graph_replay_matches_eager(anf):
         torch.cuda.synchronize()
 
 
-def test_graph_replay_of_the_widened_rows(anf):
-    """Binning, forces with the density estimate, the FP64 kernel, multipoles
+@pytest.mark.parametrize("order", ["original", "cell"])
+def test_graph_replay_of_the_widened_rows(anf, order):
+    """Binning, forces with the density estimate, the FP64 kernels, multipoles
     (both bases) and kick-drift captured in one graph: every replay, with state
-    reset and eager work between replays, equals the eager results bit for bit."""
+    reset and eager work between replays, equals the eager results bit for bit.
+    With the particles in their original order and in cell order, so both ways
+    of the kick-drift update (chosen on the device) run inside the graph."""
     boxes = synth.config("C4", scale=6)
     specs = [anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer, 0.3 * b.box / b.cpd)
              for b in boxes]
     nf = anf.NearField(specs)
     pos0 = torch.from_numpy(np.concatenate([b.pos for b in boxes])).cuda()
     vel0 = torch.from_numpy(synth.gaussian_weights(nf.n_total, 41) * np.float32(0.01)).cuda()
+    if order == "cell":
+        sort = nf.bin(pos0).perm.long()
+        pos0, vel0 = pos0[sort].contiguous(), vel0[sort].contiguous()
+    w64 = torch.from_numpy(synth.gaussian_weights(nf.n_total, 42).astype(np.float64)).cuda()
+    grad64 = torch.empty((nf.n_total, 3), dtype=torch.float64, device="cuda")
     pos, vel = pos0.clone(), vel0.clone()
     binned = nf.alloc_binned()
     acc = torch.empty((nf.n_total, 3), dtype=torch.float32, device="cuda")
@@ -170,6 +178,7 @@ def test_graph_replay_of_the_widened_rows(anf):
         nf.bin(pos, out=binned)
         nf.forces(binned, out=acc, density_out=rho)
         nf.forces_f64(binned, out=acc64)
+        nf.forces_vjp_f64(binned, w64, out=grad64)
         nf.multipoles(binned, 8, out=mp_c)
         nf.multipoles(binned, 8, reduced=True, out=mp_r)
         outs["stats"] = nf.kick_drift(binned, pos, vel, acc, 0.01, 0.002, cell_stats=True)
@@ -177,7 +186,7 @@ def test_graph_replay_of_the_widened_rows(anf):
     def snapshot():
         cs, bs = outs["stats"]
         return [t.detach().cpu().numpy().copy() for t in
-                (acc, acc64, rho, mp_c, mp_r, pos, vel, cs, bs)]
+                (acc, acc64, grad64, rho, mp_c, mp_r, pos, vel, cs, bs)]
 
     step()                    # eager reference (also allocates the lazy workspaces)
     torch.cuda.synchronize()

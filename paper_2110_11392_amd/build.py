@@ -2,7 +2,9 @@
 
 ``python -m paper_2110_11392_amd.build`` or ``build()`` compiles every HIP
 source under ``csrc/`` with hipcc for gfx950 and links the shared library that
-the Python binding loads.  Compilation runs even when a library already exists.
+the Python binding loads, then builds the plain-C example program
+``examples/nbody_step`` against the C ABI alone.  Compilation runs even when a
+library already exists.
 """
 from __future__ import annotations
 
@@ -17,6 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libabacus_nf.so")
 ARCH = "gfx950"
+EXAMPLE_SRC = os.path.join(HERE, "examples", "nbody_step.c")
+EXAMPLE = os.path.join(HERE, "examples", "nbody_step")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = ["common.hip", "bin.hip", "plan.hip", "pairs.hip", "pairs64.hip", "vjp.hip", "vjp64.hip",
            "reduce.hip",
@@ -72,7 +77,25 @@ def build(verbose: bool = False) -> str:
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
         os.replace(tmp_lib, LIB)
+    build_example(verbose)
     return LIB
+
+
+def build_example(verbose: bool = False) -> str:
+    """The C example: plain C99 host code (no HIP kernels of its own), built
+    with the system C compiler against include/abacus_nf.h, the library and
+    the HIP runtime, with the library found next to it at run time."""
+    cmd = [os.environ.get("CC", "gcc"), "-std=c99", "-O2", "-Wall", "-Wextra",
+           "-D__HIP_PLATFORM_AMD__", f"-I{INCLUDE}", f"-I{ROCM}/include", EXAMPLE_SRC,
+           f"-L{HERE}", "-labacus_nf", f"-L{ROCM}/lib", "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/..", f"-Wl,-rpath,{ROCM}/lib", "-o", EXAMPLE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":

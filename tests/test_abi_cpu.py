@@ -316,3 +316,18 @@ def test_noalloc_forces_arguments_without_gpu():
                                       None)
     assert rc == _lib.ESCRATCH
     assert "scratch" in _lib.strerror(rc)
+
+
+def test_header_and_example_are_plain_c(tmp_path):
+    """The boundary is C: include/abacus_nf.h compiles as strict C99 on its own,
+    and the C example program (paper_2110_11392_amd/examples/nbody_step.c)
+    compiles against it and the HIP runtime header with the system C compiler."""
+    import subprocess
+    from paper_2110_11392_amd import build as B
+    tu = tmp_path / "h.c"
+    tu.write_text('#include "abacus_nf.h"\nint main(void) { return 0; }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    f"-I{B.INCLUDE}", "-fsyntax-only", str(tu)], check=True)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    f"-I{B.INCLUDE}", f"-I{B.ROCM}/include", "-fsyntax-only", B.EXAMPLE_SRC],
+                   check=True)

@@ -198,3 +198,21 @@ def test_kdk_same_bits_in_either_order_ragged_batch(anf):
     outs, _, _, _ = shuffled_and_cell_order_runs(anf, boxes, kick, drift, 91)
     for x, y in zip(*outs):
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+def test_kdk_batch_of_empty_boxes(anf):
+    """No particles at all: every cell's statistics are zero, every box reports
+    N = 0, v_rms = a_max = 0 and an infinite min ratio, as the oracle does."""
+    boxes = [synth.Box(np.zeros((0, 3), np.float32), 1.0, 5, 2, 1 / 500),
+             synth.Box(np.zeros((0, 3), np.float32), 2.0, 7, 2, 2 / 500)]
+    say("[kdk] two empty boxes")
+    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer) for b in boxes])
+    empty = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    bd = nf.bin(empty)
+    cs, bs = nf.kick_drift(bd, empty, empty.clone(), empty.clone(), 0.1, 0.1, cell_stats=True)
+    cs, bs = cs.cpu().numpy(), bs.cpu().numpy()
+    assert cs.shape == (5 ** 3 + 7 ** 3, 2) and np.all(cs == 0.0)
+    for b, row in zip(boxes, bs):
+        _, _, _, ref = oracle.kick_drift(b.pos, b.pos, b.pos, b.box, b.cpd, 0.1, 0.1)
+        assert np.isinf(row[0]) and np.isinf(ref[0])
+        assert np.array_equal(row[1:], ref[1:])

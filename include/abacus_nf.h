@@ -50,6 +50,11 @@ extern "C" {
 
 /* ---- device status bits (int32 written by abacus_nf_bin) ---------------- */
 #define ABACUS_NF_STATUS_BADPOS 0x1  /* a coordinate was non-finite or |x K / L| >= 2^30 */
+/* A cell holds more than 2^28 particles: beyond the kernels' 32-bit offsets
+ * inside one cell.  The pair kernels of abacus_nf_forces, abacus_nf_forces_vjp
+ * and their FP64 variants then evaluate nothing and leave their outputs
+ * unwritten (no fault); the sizes a call accepts are otherwise unchanged. */
+#define ABACUS_NF_STATUS_CELLFULL 0x2
 
 /* ---- flags for abacus_nf_forces / abacus_nf_forces_vjp ----------------- */
 /* Accumulation of each sink's sum (exactly one of the three; default COMPENSATED):

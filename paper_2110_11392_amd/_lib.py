@@ -19,6 +19,7 @@ EHIP = -4
 ESCRATCH = -5
 
 STATUS_BADPOS = 0x1
+STATUS_CELLFULL = 0x2
 
 SINGLE_ACC = 0x1
 CHUNKED = 0x2

@@ -486,7 +486,7 @@ int forces_launch(const abacus_nf_box* boxes, int nboxes, const Resolved& r, Acc
   w.split_items = split_items_for(cfg, mode, r, L);
   {
     Timer t(3, s);
-    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span,
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, b->status, cfg.span,
                         r.split_slices, w, s),
             "work plan");
     t.done();
@@ -526,7 +526,8 @@ int abacus_nf_forces_f64(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   KernelConfig cfg = default_config(0);
   cfg.split = 0;
   w.split_items = 0;
-  ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, 1, w, s),
+  ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, b->status, cfg.span, 1, w,
+                      s),
           "work plan");
   if (r.n_total > 0) {
     Timer t(0, s);
@@ -556,7 +557,8 @@ int abacus_nf_forces_vjp_f64(const abacus_nf_box* boxes, int nboxes, const abacu
   KernelConfig cfg = default_config(1);
   cfg.split = 0;
   w.split_items = 0;
-  ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span, 1, w, s),
+  ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, b->status, cfg.span, 1, w,
+                      s),
           "work plan");
   if (r.n_total > 0) {
     Timer t(1, s);
@@ -589,7 +591,7 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   w.split_items = split_items_for(cfg, mode, r, L);
   {
     Timer t(3, s);
-    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, cfg.span,
+    ANF_HIP(launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, b->status, cfg.span,
                         r.split_slices, w, s),
             "work plan");
     t.done();
@@ -689,7 +691,7 @@ int abacus_nf_autotune(const abacus_nf_box* boxes, int nboxes, const abacus_nf_b
         err = hipEventRecord(e0, s);
         w.split_items = split_items_for(c, mode, r, L);
         if (err == hipSuccess)
-          err = launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, c.span,
+          err = launch_plan(dboxes, nboxes, r.pencils_total, b->cell_offsets, b->status, c.span,
                             r.split_slices, w, s);
         if (err == hipSuccess) {
           if (kernel == 0)

@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ b
 // would hand a long run of empty cells to a single thread).
 __global__ __launch_bounds__(256) void k_cell_offsets(const int32_t* __restrict__ sorted_keys,
                                                       int64_t n, int64_t cells,
-                                                      int32_t* __restrict__ offsets) {
+                                                      int32_t* __restrict__ offsets,
+                                                      int32_t* __restrict__ status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c > cells) return;
   int64_t lo = 0, hi = n;
@@ -53,6 +54,10 @@ __global__ __launch_bounds__(256) void k_cell_offsets(const int32_t* __restrict_
     if (sorted_keys[mid] < c) lo = mid + 1; else hi = mid;
   }
   offsets[c] = (int32_t)lo;
+  // cell c holds more than kMaxCellParticles iff its key is still found that
+  // many slots on (a load only when the array reaches that far)
+  if (lo + kMaxCellParticles < n && sorted_keys[lo + kMaxCellParticles] == c)
+    atomicOr(status, ABACUS_NF_STATUS_CELLFULL);
 }
 
 // Radix pass, step 1: per-block digit histogram, stored digit-major so that one
@@ -231,7 +236,7 @@ hipError_t launch_bin(const DevBox* boxes, int nboxes, int64_t n_total, int64_t 
   }
   // kin holds the sorted keys (the unsorted ones when no pass ran: a single cell)
   hipLaunchKernelGGL(k_cell_offsets, dim3((unsigned)((cells_total + 1 + 255) / 256)), dim3(256), 0,
-                     s, kin, n_total, cells_total, out->cell_offsets);
+                     s, kin, n_total, cells_total, out->cell_offsets, out->status);
   ANF_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gather_rel, dim3((unsigned)((n_total + 255) / 256)), dim3(256), 0, s, boxes,
                      nboxes, n_total, pos, out->perm, reinterpret_cast<float4*>(out->rel));

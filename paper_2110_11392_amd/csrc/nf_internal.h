@@ -34,6 +34,9 @@ constexpr int kCtrlNWhole = kCtrlHead + 2;
 constexpr int kCtrlNSplit = kCtrlHead + 3;
 constexpr int kCtrlSlices = kCtrlHead + 4;
 constexpr int kCtrlInts = kCtrlHead + 8;
+// Most particles one cell may hold: the pair kernels form record offsets
+// inside a cell (up to 6 floats per particle) in 32 bits.
+constexpr int64_t kMaxCellParticles = int64_t(1) << 28;
 // Radix sort: 8-bit digits, 256 threads x 16 keys per block.
 constexpr int kRadixBits = 8;
 constexpr int kRadixThreads = 256;
@@ -333,9 +336,11 @@ int64_t plan_max_tasks(int64_t max_items, int64_t max_split);
 int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_total);
 // w.split_items of the cheapest items are split into `slices` = 2R+1 x-offset
 // tasks (every box must share R <= 3 when w.split_items > 0).
+// status: the binning's status word; with ABACUS_NF_STATUS_CELLFULL set the
+// task list is empty.
 hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils_total,
-                       const int32_t* cell_offsets, int span, int slices, const PlanWork& w,
-                       hipStream_t s);
+                       const int32_t* cell_offsets, const int32_t* status, int span, int slices,
+                       const PlanWork& w, hipStream_t s);
 // Combine the slices of split items into final outputs (adjoint: 1/w^3 scale;
 // density: NULL or the density output of the forward kernel).
 hipError_t launch_combine(AccMode mode, bool adjoint, const DevBox* boxes, const PlanWork& w,

@@ -161,15 +161,16 @@ __global__ __launch_bounds__(256) void k_item_cost(const DevBox* __restrict__ bo
 
 // Bucket bases (longest first) and the task-list layout: the cheapest
 // split_items items of the queue are split into `slices` x-offset tasks each.
+// A binning that found a cell beyond kMaxCellParticles leaves no task at all.
 __global__ void k_bucket_scan(int32_t* __restrict__ ctrl, const int32_t* __restrict__ n_items_ptr,
-                              int split_items, int slices) {
+                              const int32_t* __restrict__ status, int split_items, int slices) {
   if (threadIdx.x != 0) return;
   int run = 0;
   for (int k = 0; k < kBuckets; ++k) {
     ctrl[kBuckets + k] = run;
     run += ctrl[k];
   }
-  const int n_items = *n_items_ptr;
+  const int n_items = (*status & ABACUS_NF_STATUS_CELLFULL) ? 0 : *n_items_ptr;
   int split = slices >= 2 ? split_items : 0;
   split = split < n_items / 2 ? split : n_items / 2;
   ctrl[kCtrlHead] = 0;
@@ -264,7 +265,8 @@ int64_t plan_max_items(int64_t n_total, int64_t cells_total, int64_t pencils_tot
   } while (0)
 
 hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils, const int32_t* off,
-                       int span, int slices, const PlanWork& w, hipStream_t s) {
+                       const int32_t* status, int span, int slices, const PlanWork& w,
+                       hipStream_t s) {
   span = span < 1 ? 1 : (span > kMaxSpan ? kMaxSpan : span);
   const unsigned gp = (unsigned)pencils;  // one wave per pencil
   hipLaunchKernelGGL(k_plan_count, dim3(gp), dim3(64), 0, s, boxes, nboxes, pencils, off, span,
@@ -281,7 +283,7 @@ hipError_t launch_plan(const DevBox* boxes, int nboxes, int64_t pencils, const i
                      w.item_bucket, w.item_slot, w.item_cost, w.ctrl);
   ANF_TRY(hipGetLastError());
   const int split = (int)(w.split_items < w.max_split ? w.split_items : w.max_split);
-  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, s, w.ctrl, n_items,
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(64), 0, s, w.ctrl, n_items, status,
                      slices >= 2 && slices <= kMaxSlices ? split : 0, slices);
   ANF_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_task_scatter, dim3(gi), dim3(256), 0, s, n_items, w.item_bucket,

@@ -57,10 +57,14 @@ class Binned:
                            self.rel.data_ptr(), self.status.data_ptr())
 
     def check_status(self) -> None:
-        """Raise if the binning flagged bad coordinates (synchronises)."""
+        """Raise if the binning flagged bad coordinates, or a cell too full for
+        the pair kernels, which then evaluate nothing (synchronises)."""
         st = int(self.status.item())
         if st & _lib.STATUS_BADPOS:
             raise ValueError("non-finite or out-of-range particle coordinate (|x K/L| >= 2^30)")
+        if st & _lib.STATUS_CELLFULL:
+            raise ValueError("a cell holds more than 2^28 particles: beyond the pair kernels' "
+                             "offsets; use more cells per dimension")
 
 
 def _stream() -> ctypes.c_void_p:

@@ -26,6 +26,13 @@ def test_header_declares_the_boundary():
         assert required in names
 
 
+def test_status_bits_match_the_header():
+    text = open(HEADER).read()
+    bits = {m.group(1): int(m.group(2), 0)
+            for m in re.finditer(r"#define ABACUS_NF_STATUS_(\w+)\s+(0x[0-9a-fA-F]+)", text)}
+    assert bits == {"BADPOS": _lib.STATUS_BADPOS, "CELLFULL": _lib.STATUS_CELLFULL}
+
+
 def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in header_functions():

@@ -309,6 +309,22 @@ def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
     a64 = kernel_ms(1, lambda: nf.forces_vjp_f64(st.binned, w64, out=acc64))
     rows["fp64_adjoint"] = {"adjoint_ms": a64, "vs_fp32": a64 / adj}
     del acc64, w64
+    # one GPU's share of a box split into slabs along x: 8 shares of K/8 sink
+    # slabs, each reading its neighbour slabs, forward and adjoint per share
+    if len(boxes) == 1 and boxes[0].cpd % 8 == 0:
+        K = boxes[0].cpd
+        shares = [(g * K // 8, (g + 1) * K // 8) for g in range(8)]
+        f_sh = [kernel_ms(0, lambda x=x: nf.forces_slab(st.binned, x[0], x[1], accumulation,
+                                                        out=st.acc)) for x in shares]
+        a_sh = [kernel_ms(1, lambda x=x: nf.forces_vjp_slab(st.binned, x[0], x[1], st.wvec,
+                                                            accumulation, out=st.acc))
+                for x in shares]
+        rows["slab_shares"] = {
+            "shares": 8, "sink_slabs_per_share": K // 8,
+            "forward_ms": f_sh, "adjoint_ms": a_sh,
+            "forward_sum_over_whole": sum(f_sh) / fwd, "adjoint_sum_over_whole": sum(a_sh) / adj,
+            "forward_max_over_mean": max(f_sh) * 8 / sum(f_sh),
+            "adjoint_max_over_mean": max(a_sh) * 8 / sum(a_sh)}
     # multipoles, p = 8
     n, cells = nf.n_total, nf.cells_total
     out_c = torch.empty((cells, 165), dtype=torch.float64, device=dev)

@@ -232,6 +232,28 @@ int abacus_nf_forces_vjp(const abacus_nf_box *boxes, int nboxes, const abacus_nf
                          const float *w, float *grad, uint32_t flags, void *ws,
                          size_t ws_bytes, void *stream);
 
+/*
+ * abacus_nf_forces_slab / abacus_nf_forces_vjp_slab -- abacus_nf_forces and
+ * abacus_nf_forces_vjp for the sinks of the slabs x in [x_begin, x_end) of
+ * every box only.  The near field is evaluated one sink slab at a time, with
+ * the R source slabs on either side resident (Sec. 3.4.1), and a node of a
+ * parallel run holds a range of slabs (Sec. 4.4): this is one such share.
+ * Sources still come from every cell of each sink's stencil, so those
+ * slabs' outputs are bit-identical to the whole-box call's; the entries of
+ * acc / grad for particles outside the slabs are not written.
+ *   x_begin, x_end  0 <= x_begin <= x_end <= K of every box (else EINVAL);
+ *                   x_begin == x_end computes nothing.
+ *   flags           accumulation flags and ABACUS_NF_PLUMMER (COUNT_PAIRS:
+ *                   EINVAL).  Same binned arrays and workspace as the
+ *                   whole-box calls; other arguments and errors as those.
+ */
+int abacus_nf_forces_slab(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                          int32_t x_begin, int32_t x_end, float *acc, uint32_t flags, void *ws,
+                          size_t ws_bytes, void *stream);
+int abacus_nf_forces_vjp_slab(const abacus_nf_box *boxes, int nboxes, const abacus_nf_binned *b,
+                              int32_t x_begin, int32_t x_end, const float *w, float *grad,
+                              uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
 /* Human-readable text for an error code; for ABACUS_NF_EHIP it includes the
  * message of the last failing HIP call on this thread. */
 const char *abacus_nf_strerror(int code);

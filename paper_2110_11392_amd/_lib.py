@@ -66,7 +66,8 @@ EXPORTS = ("abacus_nf_layout", "abacus_nf_workspace_bytes", "abacus_nf_bin", "ab
            "abacus_nf_timing_read", "abacus_nf_timing_reset", "abacus_nf_multipole_terms",
            "abacus_nf_multipoles_workspace_bytes", "abacus_nf_multipoles",
            "abacus_nf_kick_drift_workspace_bytes", "abacus_nf_kick_drift", "abacus_nf_timestep",
-           "abacus_nf_forces_f64", "abacus_nf_forces_vjp_f64", "abacus_nf_forces_noalloc")
+           "abacus_nf_forces_f64", "abacus_nf_forces_vjp_f64", "abacus_nf_forces_noalloc",
+           "abacus_nf_forces_slab", "abacus_nf_forces_vjp_slab")
 
 _lib = None
 
@@ -99,6 +100,10 @@ def load() -> ctypes.CDLL:
     lib.abacus_nf_forces_vjp_f64.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, u32, vp, sz,
                                              vp]
     lib.abacus_nf_forces_noalloc.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, vp, vp, vp, u32, vp]
+    lib.abacus_nf_forces_slab.argtypes = [BoxP, ctypes.c_int, BinnedP, i32, i32, vp, u32, vp, sz,
+                                          vp]
+    lib.abacus_nf_forces_vjp_slab.argtypes = [BoxP, ctypes.c_int, BinnedP, i32, i32, vp, vp, u32,
+                                              vp, sz, vp]
     TuneP = ctypes.POINTER(Tuning)
     lib.abacus_nf_autotune.argtypes = [BoxP, ctypes.c_int, BinnedP, vp, u32, vp, sz, vp, TuneP,
                                        TuneP]

@@ -75,6 +75,8 @@ int resolve(const abacus_nf_box* in, int nboxes, Resolved* out, bool plummer = f
     std::memset(&d, 0, sizeof(d));
     d.first = n_total;
     d.n = x.n;
+    d.sink_x0 = 0;
+    d.sink_x1 = (int32_t)K;
     d.cell_base = (int32_t)cells_total;
     d.K = (int32_t)K;
     d.R = x.radius;
@@ -344,6 +346,10 @@ int forces_launch(const abacus_nf_box* boxes, int nboxes, const Resolved& r, Acc
                   bool count, const abacus_nf_binned* b, float* acc, float* density,
                   double* momentum, int64_t* pair_count, void* ws, const Layout& L,
                   hipStream_t s);
+int vjp_call(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b, bool slab,
+             int32_t x0, int32_t x1, const float* wv, float* grad, uint32_t flags, void* ws,
+             size_t ws_bytes, void* stream);
+int set_sink_slabs(Resolved* r, int32_t x0, int32_t x1);
 
 // ---- the static scratch of abacus_nf_forces_noalloc -----------------------
 // Every GPU the library runs on holds its own copy of this array until the
@@ -574,6 +580,39 @@ int abacus_nf_forces_vjp_f64(const abacus_nf_box* boxes, int nboxes, const abacu
 int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
                          const float* wv, float* grad, uint32_t flags, void* ws, size_t ws_bytes,
                          void* stream) {
+  return vjp_call(boxes, nboxes, b, false, 0, 0, wv, grad, flags, ws, ws_bytes, stream);
+}
+
+int abacus_nf_forces_slab(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                          int32_t x_begin, int32_t x_end, float* acc, uint32_t flags, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (flags & ABACUS_NF_COUNT_PAIRS) return ABACUS_NF_EINVAL;
+  Resolved r;
+  AccMode mode;
+  int rc = forces_args(boxes, nboxes, b, acc, nullptr, nullptr, flags, &r, &mode);
+  if (rc) return rc;
+  if ((rc = set_sink_slabs(&r, x_begin, x_end))) return rc;
+  const Layout L = layout(r);
+  if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+  return forces_launch(boxes, nboxes, r, mode, false, b, acc, nullptr, nullptr, nullptr, ws, L,
+                       static_cast<hipStream_t>(stream));
+}
+
+int abacus_nf_forces_vjp_slab(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b,
+                              int32_t x_begin, int32_t x_end, const float* wv, float* grad,
+                              uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  return vjp_call(boxes, nboxes, b, true, x_begin, x_end, wv, grad, flags, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// abacus_nf_forces_vjp, or with `slab` its variant for the sink slabs
+// [x0, x1) of every box.
+int vjp_call(const abacus_nf_box* boxes, int nboxes, const abacus_nf_binned* b, bool slab,
+             int32_t x0, int32_t x1, const float* wv, float* grad, uint32_t flags, void* ws,
+             size_t ws_bytes, void* stream) {
   Resolved r;
   int rc = resolve(boxes, nboxes, &r, (flags & ABACUS_NF_PLUMMER) != 0);
   if (rc) return rc;
@@ -581,6 +620,7 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   if ((rc = acc_mode(flags, &mode))) return rc;
   if (flags & ABACUS_NF_COUNT_PAIRS) return ABACUS_NF_EINVAL;
   if (!binned_ok(b, r.n_total) || (r.n_total > 0 && (!wv || !grad))) return ABACUS_NF_EINVAL;
+  if (slab && (rc = set_sink_slabs(&r, x0, x1))) return rc;
   const Layout L = layout(r);
   if ((rc = check_ws(ws, ws_bytes, L))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -605,6 +645,21 @@ int abacus_nf_forces_vjp(const abacus_nf_box* boxes, int nboxes, const abacus_nf
   }
   return ABACUS_NF_OK;
 }
+
+// The sink slabs [x0, x1) of every box (0 <= x0 <= x1 <= K): the work plan
+// then takes only the pencils of those slabs.
+int set_sink_slabs(Resolved* r, int32_t x0, int32_t x1) {
+  for (DevBox& d : r->boxes) {
+    if (x0 < 0 || x0 > x1 || x1 > d.K) return ABACUS_NF_EINVAL;
+    d.sink_x0 = x0;
+    d.sink_x1 = x1;
+  }
+  return ABACUS_NF_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 static abacus_nf_tuning to_public(const KernelConfig& c) {
   abacus_nf_tuning t;

@@ -116,6 +116,7 @@ struct DevBox {
   double kick, drift;   // kick-drift step factors of this call
   double eps_cells64;   // the FP64 kernel's softening in cell widths: eps_s (Eq. 3) or eps_p (Eq. 2)
   float near2;          // (1.1 eps)^2 in cell units: pairs beyond it take 1/r^3 without the select
+  int32_t sink_x0, sink_x1;  // the work plan takes sinks of the slabs x in [sink_x0, sink_x1) only
   int32_t pad2_;
 };
 constexpr int kFarNone = 0, kFarApart = 1, kFarAll = 2;
@@ -126,6 +127,7 @@ struct BoxChunk {
   int count;
   int offset;
 };
+static_assert(sizeof(BoxChunk) <= 4096, "a box chunk is passed as one kernel argument");
 
 // Locate the box owning a value v among nb boxes given a monotone key.
 __device__ __forceinline__ int find_box_by_first(const DevBox* __restrict__ boxes, int nb,

@@ -54,6 +54,10 @@ __device__ void plan_pencil(const DevBox* __restrict__ boxes, int nboxes, int64_
   const int K = boxes[b].K;
   const int local = (int)p - boxes[b].pencil_base;
   const int cx = local / K, cy = local - (local / K) * K;
+  if (cx < boxes[b].sink_x0 || cx >= boxes[b].sink_x1) {  // outside the sink slabs: no items
+    if (!kEmit && threadIdx.x == 0) counts[p] = 0;
+    return;
+  }
   const int cell0 = boxes[b].cell_base + local * K;
   for (int z = threadIdx.x; z <= K; z += blockDim.x) po[z] = off[cell0 + z];
   __syncthreads();

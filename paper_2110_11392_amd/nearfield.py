@@ -215,6 +215,48 @@ class NearField:
                    "abacus_nf_forces_vjp")
         return grad
 
+    def _slab_out(self, out: Optional[torch.Tensor]) -> torch.Tensor:
+        if out is None:
+            return torch.empty((self.n_total, 3), dtype=torch.float32, device=self.device)
+        if out.dtype != torch.float32 or tuple(out.shape) != (self.n_total, 3) or \
+                not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous (n, 3) float32 tensor on the device")
+        return out
+
+    def forces_slab(self, binned: Binned, x_begin: int, x_end: int,
+                    accumulation: str = "compensated",
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Accelerations of the sinks in the slabs x in [x_begin, x_end) of every
+        box, bit-identical to those rows of ``forces``; other rows of ``out``
+        are left as they were (uninitialised when ``out`` is None)."""
+        acc = self._slab_out(out)
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_forces_slab(self._boxes, self.nboxes, ctypes.byref(cs),
+                                                   int(x_begin), int(x_end), _ptr(acc),
+                                                   self._flags(accumulation),
+                                                   _ptr(self.workspace), self.workspace_bytes,
+                                                   _stream()),
+                   "abacus_nf_forces_slab")
+        return acc
+
+    def forces_vjp_slab(self, binned: Binned, x_begin: int, x_end: int, w: torch.Tensor,
+                        accumulation: str = "compensated",
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """``forces_vjp`` for the particles of the slabs x in [x_begin, x_end)
+        of every box; other rows of ``out`` are left as they were."""
+        if w.dtype != torch.float32 or tuple(w.shape) != (self.n_total, 3) or not w.is_contiguous():
+            raise ValueError("cotangent must be a contiguous (n, 3) float32 tensor")
+        grad = self._slab_out(out)
+        cs = binned.cstruct()
+        _lib.check(self._lib.abacus_nf_forces_vjp_slab(self._boxes, self.nboxes,
+                                                       ctypes.byref(cs), int(x_begin), int(x_end),
+                                                       _ptr(w), _ptr(grad),
+                                                       self._flags(accumulation),
+                                                       _ptr(self.workspace),
+                                                       self.workspace_bytes, _stream()),
+                   "abacus_nf_forces_vjp_slab")
+        return grad
+
 
     def multipoles(self, binned: Binned, order: int, reduced: bool = False,
                    out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -302,6 +302,39 @@ def test_fp64_adjoint_arguments_without_gpu():
                                         None, nbytes, None) == _lib.EWORKSPACE
 
 
+def test_slab_arguments_without_gpu():
+    """The slab variants take 0 <= x_begin <= x_end <= K of every box, refuse
+    the pair counter, and otherwise validate like the whole-box calls, all
+    before any HIP call."""
+    lib = _lib.load()
+    b2 = boxes((100, 1.0, 8, 2, 1e-3), (50, 1.0, 6, 2, 1e-3))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.abacus_nf_workspace_bytes(b2, 2, ctypes.byref(nbytes)) == 0
+    fake = ctypes.c_void_p(0x1000)
+    binned = _lib.Binned(0x1000, 0x1000, 0x1000, 0x1000)
+
+    def fwd(x0, x1, acc=fake, flags=_lib.COMPENSATED, ws=fake, box=b2, n=2):
+        return lib.abacus_nf_forces_slab(box, n, ctypes.byref(binned), x0, x1, acc, flags, ws,
+                                         nbytes, None)
+
+    def adj(x0, x1, w=fake, g=fake, flags=_lib.COMPENSATED, ws=fake):
+        return lib.abacus_nf_forces_vjp_slab(b2, 2, ctypes.byref(binned), x0, x1, w, g, flags,
+                                             ws, nbytes, None)
+
+    for x0, x1 in ((-1, 3), (4, 3), (0, 7), (7, 7), (0, 2 ** 31 - 1)):  # K = 6 bounds box 2
+        assert fwd(x0, x1) == _lib.EINVAL, (x0, x1)
+        assert adj(x0, x1) == _lib.EINVAL, (x0, x1)
+    for x0, x1 in ((0, 6), (6, 6), (2, 3)):
+        assert fwd(x0, x1, ws=None) == _lib.EWORKSPACE
+        assert adj(x0, x1, ws=None) == _lib.EWORKSPACE
+    assert fwd(0, 6, flags=_lib.COMPENSATED | _lib.COUNT_PAIRS) == _lib.EINVAL
+    assert adj(0, 6, flags=_lib.COMPENSATED | _lib.COUNT_PAIRS) == _lib.EINVAL
+    assert fwd(0, 6, flags=_lib.SINGLE_ACC | _lib.CHUNKED) == _lib.EINVAL
+    assert fwd(0, 6, acc=None) == _lib.EINVAL
+    assert adj(0, 6, w=None) == _lib.EINVAL and adj(0, 6, g=None) == _lib.EINVAL
+    assert fwd(0, 4, box=boxes((100, 1.0, 4, 2, 1e-3)), n=1) == _lib.EINVAL  # K < 2R+1
+
+
 def test_noalloc_forces_arguments_without_gpu():
     """The no-allocation entry point validates like abacus_nf_forces and refuses
     a problem its static scratch cannot hold, all before any HIP call."""

@@ -51,9 +51,11 @@ extern "C" {
 /* ---- device status bits (int32 written by abacus_nf_bin) ---------------- */
 #define ABACUS_NF_STATUS_BADPOS 0x1  /* a coordinate was non-finite or |x K / L| >= 2^30 */
 /* A cell holds more than 2^28 particles: beyond the kernels' 32-bit offsets
- * inside one cell.  The pair kernels of abacus_nf_forces, abacus_nf_forces_vjp
- * and their FP64 variants then evaluate nothing and leave their outputs
- * unwritten (no fault); the sizes a call accepts are otherwise unchanged. */
+ * inside one cell.  Every call that runs the pair kernels on these binned
+ * arrays (abacus_nf_forces, abacus_nf_forces_vjp and their FP64, slab and
+ * no-allocation variants) then evaluates no pair: accelerations and gradients
+ * are not written, and momentum sums add whatever the acceleration array held.
+ * Nothing faults; the sizes a call accepts are otherwise unchanged. */
 #define ABACUS_NF_STATUS_CELLFULL 0x2
 
 /* ---- flags for abacus_nf_forces / abacus_nf_forces_vjp ----------------- */

@@ -68,6 +68,8 @@ def boxes(*specs):
     ((100, 1.0, 1300, 2, 1e-3), _lib.ERANGE),        # K^3 >= 2^31
     ((100, 1.0, 600, 2, 1e-3), _lib.OK),             # 2.2e8 cells: work plan < 2^28 items
     ((100, 1.0, 650, 2, 1e-3), _lib.ERANGE),         # 2.7e8 cells: work plan may reach 2^28
+    ((100, 1.0, 644, 2, 1e-3), _lib.OK),             # the largest grid the plan takes
+    ((100, 1.0, 645, 2, 1e-3), _lib.ERANGE),
 ])
 def test_layout_validation(spec, code):
     lib = _lib.load()

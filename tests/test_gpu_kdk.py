@@ -84,6 +84,15 @@ def test_kdk_c1(anf):
     run_case(anf, synth.config("C1"), 0.01, 0.02)
 
 
+def test_kdk_largest_grid(anf):
+    """K = 644, the largest grid the library takes: 267 M cells, almost all
+    empty (their statistics zero), about 5 x 10^5 statistics chunks."""
+    K = 644
+    pos = np.concatenate([synth.uniform(32768, 7001), synth.clustered(32768, 16, K, 7002)])
+    say(f"[kdk] K={K}, {pos.shape[0]} particles")
+    run_case(anf, [synth.Box(pos, 1.0, K, 2, 1.0 / (40 * 4096.0))], 0.01, 0.02)
+
+
 def test_kdk_wraps_and_big_steps(anf):
     say("[kdk] clustered K9, drift of several boxes")
     boxes = [synth.Box(synth.clustered(5000, 12, 9, 10), 1.0, 9, 1, 1 / 700)]

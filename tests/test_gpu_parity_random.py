@@ -100,3 +100,53 @@ def test_random_configuration(anf, case):
         say(f"  forces {st}; adjoint relative error {rel_g:.3g}")
         assert st["median"] <= MEDIAN_TOL and st["p999"] <= P999_TOL
         assert rel_g <= VJP_TOL
+
+
+def dyadic(pos):
+    q = np.floor(np.asarray(pos, np.float64) * 2.0 ** 20) / 2.0 ** 20
+    q[q >= 1.0] = 0.0
+    return q.astype(np.float32)
+
+
+# FP64 kernels at the radii and grids above, on dyadic positions (L = 1, K a
+# power of two): the stored FP32 cell offsets are then exact, so the FP64
+# kernels must match the oracle to FP64 rounding, forces within 1e-12 at the
+# median and 1e-9 at the maximum, the adjoint within 1e-12 in relative 2-norm.
+FP64_CASES = {
+    "K1_R0": [(2000, 1, 0, 0.02)],
+    "K2_R0": [(1500, 2, 0, 0.3)],
+    "K8_R3": [(3000, 8, 3, 0.01)],
+    "K16_R4": [(3000, 16, 4, 0.04)],
+    "mixed_R": [(1200, 4, 1, 0.05), (0, 2, 0, 0.1), (2500, 8, 3, 0.7), (1800, 16, 4, 0.01)],
+}
+
+
+@pytest.mark.parametrize("law", ["spline", "plummer"])
+@pytest.mark.parametrize("name", list(FP64_CASES))
+def test_fp64_radii_and_grids(anf, name, law):
+    specs = FP64_CASES[name]
+    boxes = [synth.Box(dyadic(synth.clustered(n, max(1, n // 300), K, 9400 + k)), 1.0, K, R,
+                       eps_cells / 2.16 / K)
+             for k, (n, K, R, eps_cells) in enumerate(specs)]
+    say(f"[random fp64] {name} {law}")
+    nf = anf.NearField([anf.BoxSpec(b.n, b.box, b.cpd, b.radius, b.eps_plummer) for b in boxes],
+                       law=law)
+    bd = nf.bin(torch.from_numpy(np.ascontiguousarray(np.concatenate([b.pos for b in boxes])))
+                .cuda())
+    w32 = synth.gaussian_weights(nf.n_total, 9500)
+    w = w32.astype(np.float64)   # the same values: the oracle takes them in FP32
+    acc = nf.forces_f64(bd).cpu().numpy()
+    grad = nf.forces_vjp_f64(bd, torch.from_numpy(w).cuda()).cpu().numpy()
+    first = 0
+    for b in boxes:
+        if b.n:
+            sl = slice(first, first + b.n)
+            ref, _ = oracle.forces(b.pos, 1.0, b.cpd, b.radius, b.eps_plummer, law=law)
+            gref = oracle.vjp(b.pos, w32[sl], 1.0, b.cpd, b.radius, b.eps_plummer, law=law)
+            st = err_stats(frac_err(acc[sl], ref))
+            rel2 = np.linalg.norm(grad[sl] - gref) / np.linalg.norm(gref)
+            say(f"  n={b.n} K={b.cpd} R={b.radius}: forces {st}; adjoint relative 2-norm "
+                f"{rel2:.3g}")
+            assert st["median"] <= 1e-12 and st["max"] <= 1e-9
+            assert rel2 <= 1e-12
+        first += b.n

@@ -225,3 +225,24 @@ def test_kdk_batch_of_empty_boxes(anf):
         _, _, _, ref = oracle.kick_drift(b.pos, b.pos, b.pos, b.box, b.cpd, 0.1, 0.1)
         assert np.isinf(row[0]) and np.isinf(ref[0])
         assert np.array_equal(row[1:], ref[1:])
+
+
+@pytest.mark.parametrize("i", range(8))
+def test_kdk_random(anf, i):
+    """Seeded random batches: one to three boxes, K 1..12, sides 0.3, 1 and 2.5,
+    0 to 3000 particles, and per-box kick and drift factors drawn from
+    [-0.5, 0.5] and [-30, 30] (drifts of many box lengths, both directions)."""
+    rng = np.random.default_rng(9900 + i)
+    boxes, kicks, drifts = [], [], []
+    for k in range(int(rng.integers(1, 4))):
+        K = int(rng.integers(1, 13))
+        L = float(rng.choice([0.3, 1.0, 2.5]))
+        n = int(rng.integers(0, 3001))
+        seed = 9950 + 10 * i + k
+        pos = synth.uniform(n, seed, L) if rng.random() < 0.5 else \
+            synth.clustered(n, max(1, n // 250), K, seed, L)
+        boxes.append(synth.Box(pos, L, K, 0, L / K / 100))
+        kicks.append(float(rng.uniform(-0.5, 0.5)))
+        drifts.append(float(rng.uniform(-30.0, 30.0)))
+    say(f"[kdk] random {i}: " + ", ".join(f"n={b.n} K={b.cpd} L={b.box}" for b in boxes))
+    run_case(anf, boxes, kicks, drifts, seed=9990 + i)

@@ -128,3 +128,37 @@ def test_multipoles_reject_bad_arguments(anf):
         nf.multipoles(bd, 9)
     with pytest.raises(Exception):
         nf.multipoles(bd, -1)
+
+
+def random_boxes(i):
+    """One to three boxes from a seeded generator: K 1..12 (R plays no part in
+    the multipoles), sides 0.3, 1 and 2.5, 0 to 3000 particles uniform,
+    clustered or piled into a few cells."""
+    rng = np.random.default_rng(9600 + i)
+    boxes = []
+    for k in range(int(rng.integers(1, 4))):
+        K = int(rng.integers(1, 13))
+        L = float(rng.choice([0.3, 1.0, 2.5]))
+        n = int(rng.integers(0, 3001))
+        seed = 9700 + 10 * i + k
+        kind = int(rng.integers(3))
+        if kind == 0:
+            pos = synth.uniform(n, seed, L)
+        elif kind == 1:
+            pos = synth.clustered(n, max(1, n // 250), K, seed, L)
+        else:   # a few crowded cells: up to n particles in one cell
+            pos = ((np.float32(0.5) + np.float32(0.004) * synth.uniform(n, seed)) *
+                   np.float32(L)).astype(np.float32)
+        boxes.append(synth.Box(pos, L, K, 0, L / K / 100))
+    return boxes
+
+
+@pytest.mark.parametrize("i", range(8))
+def test_multipoles_random(anf, i):
+    boxes = random_boxes(i)
+    p = int(np.random.default_rng(9800 + i).integers(0, 9))
+    say(f"[multipoles] random {i} p={p}: " +
+        ", ".join(f"n={b.n} K={b.cpd} L={b.box}" for b in boxes))
+    for reduced in (False, True):
+        _, _, got = run(anf, boxes, p, reduced)
+        check(boxes, p, reduced, got)

@@ -33,6 +33,7 @@ the widened rows (density, Plummer, FP64 kernel, multipoles, kick-drift) on C3.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -376,6 +377,19 @@ def measure_rows(anf, torch, st, boxes, accumulation, reps=5):
     return rows
 
 
+def binning_row(ms, n, cells, step_ms):
+    """The binning against the HBM line.  Algorithmic bytes: the position read
+    twice (cell assignment, then the cell offsets of the sorted slots), the
+    cell id written and read back, the 16-byte offsets and 4-byte permutation
+    written (52 B per particle), and 4 B of cell offset per cell.  The stable
+    LSD radix sort moves 24 B per particle in each of its 8-bit passes."""
+    bits = max(1, math.ceil(math.log2(max(cells, 2))))
+    b = 52.0 * n + 4.0 * (cells + 1)
+    return {"ms": ms, "algorithmic_bytes": b, "gbps": b / (ms * 1e-3) / 1e9,
+            "frac_hbm": b / (ms * 1e-3) / 8e12, "radix_passes": (bits + 7) // 8,
+            "share_of_step": ms / step_ms}
+
+
 def timed(torch, fn, steps):
     stream = torch.cuda.current_stream()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -589,6 +603,7 @@ def main():
         "particle_updates_per_s": nf.n_total / ((avg["bin"] + avg["plan"] + avg["forward"]) * 1e-3),
         "adjoint_over_forward": avg["adjoint"] / avg["forward"],
         "kernel_ms": avg,
+        "binning": binning_row(avg["bin"], nf.n_total, nf.cells_total, ms_value),
         "momentum_residual": resid,
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

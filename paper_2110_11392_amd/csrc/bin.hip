@@ -15,6 +15,33 @@
 
 namespace anf {
 
+// The box of particle (or sorted slot) i.  A block covers consecutive indices;
+// it stages the boxes' first indices in LDS once (up to kLdsBoxes boxes), and
+// each thread's binary search then reads LDS instead of walking a chain of
+// dependent global loads (six of them for 64 boxes).  Larger batches search
+// the box table itself.
+constexpr int kLdsBoxes = 1024;
+
+__device__ __forceinline__ void stage_box_firsts(const DevBox* __restrict__ boxes, int nboxes,
+                                                 int64_t* s_first) {
+  if (nboxes > 1 && nboxes <= kLdsBoxes) {  // uniform over the block
+    for (int k = threadIdx.x; k < nboxes; k += blockDim.x) s_first[k] = boxes[k].first;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int box_of(const DevBox* __restrict__ boxes, int nboxes,
+                                      const int64_t* s_first, int64_t i) {
+  if (nboxes == 1) return 0;
+  if (nboxes > kLdsBoxes) return find_box_by_first(boxes, nboxes, i);
+  int lo = 0, hi = nboxes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_first[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Pass 1: global cell id per particle and key/value init.  (No per-cell
 // counting here: device-wide atomics on the counts of crowded cells cost more
 // than the whole radix sort; the offsets are found in the sorted keys instead.)
@@ -23,9 +50,11 @@ __global__ __launch_bounds__(256) void k_bin_assign(const DevBox* __restrict__ b
                                                     int32_t* __restrict__ keys,
                                                     int32_t* __restrict__ vals,
                                                     int32_t* __restrict__ status) {
+  __shared__ int64_t s_first[kLdsBoxes];
+  stage_box_firsts(boxes, nboxes, s_first);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_total) return;
-  const int b = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, i);
+  const int b = box_of(boxes, nboxes, s_first, i);
   const double cpl = boxes[b].cells_per_len;
   const int K = boxes[b].K;
   const CellCoord x = cell_coord(pos[3 * i + 0], cpl, K);
@@ -166,9 +195,11 @@ __global__ __launch_bounds__(256) void k_gather_rel(const DevBox* __restrict__ b
                                                     int64_t n_total, const float* __restrict__ pos,
                                                     const int32_t* __restrict__ perm,
                                                     float4* __restrict__ rel) {
+  __shared__ int64_t s_first[kLdsBoxes];
+  stage_box_firsts(boxes, nboxes, s_first);
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_total) return;
-  const int b = nboxes == 1 ? 0 : find_box_by_first(boxes, nboxes, s);
+  const int b = box_of(boxes, nboxes, s_first, s);
   const double cpl = boxes[b].cells_per_len;
   const int K = boxes[b].K;
   const int64_t i = perm[s];

@@ -149,8 +149,9 @@ def test_graph_replay_matches_eager(anf):
 
 @pytest.mark.parametrize("order", ["original", "cell"])
 def test_graph_replay_of_the_widened_rows(anf, order):
-    """Binning, forces with the density estimate, the FP64 kernels, multipoles
-    (both bases) and kick-drift captured in one graph: every replay, with state
+    """Binning, forces with the density estimate, the FP64 kernels, slab shares
+    of the FP32 forward and adjoint, multipoles (both bases) and kick-drift
+    captured in one graph: every replay, with state
     reset and eager work between replays, equals the eager results bit for bit.
     With the particles in their original order and in cell order, so both ways
     of the kick-drift update (chosen on the device) run inside the graph."""
@@ -172,6 +173,10 @@ def test_graph_replay_of_the_widened_rows(anf, order):
     rho = torch.empty(nf.n_total, dtype=torch.float32, device="cuda")
     mp_c = torch.empty((nf.cells_total, 165), dtype=torch.float64, device="cuda")
     mp_r = torch.empty((nf.cells_total, 81), dtype=torch.float64, device="cuda")
+    w32 = torch.from_numpy(synth.gaussian_weights(nf.n_total, 43)).cuda()
+    # rows outside the slabs are never written: NaN throughout, in every replay
+    slab_acc = torch.full((nf.n_total, 3), float("nan"), dtype=torch.float32, device="cuda")
+    slab_grad = torch.full_like(slab_acc, float("nan"))
     outs = {}
 
     def step():
@@ -179,6 +184,8 @@ def test_graph_replay_of_the_widened_rows(anf, order):
         nf.forces(binned, out=acc, density_out=rho)
         nf.forces_f64(binned, out=acc64)
         nf.forces_vjp_f64(binned, w64, out=grad64)
+        nf.forces_slab(binned, 1, 4, out=slab_acc)
+        nf.forces_vjp_slab(binned, 2, 6, w32, out=slab_grad)
         nf.multipoles(binned, 8, out=mp_c)
         nf.multipoles(binned, 8, reduced=True, out=mp_r)
         outs["stats"] = nf.kick_drift(binned, pos, vel, acc, 0.01, 0.002, cell_stats=True)
@@ -186,7 +193,7 @@ def test_graph_replay_of_the_widened_rows(anf, order):
     def snapshot():
         cs, bs = outs["stats"]
         return [t.detach().cpu().numpy().copy() for t in
-                (acc, acc64, grad64, rho, mp_c, mp_r, pos, vel, cs, bs)]
+                (acc, acc64, grad64, rho, mp_c, mp_r, pos, vel, cs, bs, slab_acc, slab_grad)]
 
     step()                    # eager reference (also allocates the lazy workspaces)
     torch.cuda.synchronize()

@@ -39,7 +39,8 @@ def test_largest_grid_against_oracle():
     pos = np.concatenate([synth.uniform(n_u, 7001), synth.clustered(n_c, 16, K, 7002)])
     n = pos.shape[0]
     nf = anf.NearField([anf.BoxSpec(n, 1.0, K, 2, EPS_P)])
-    say(f"[max grid] n={n} K={K} ({K ** 3} cells); workspace {nf.workspace_bytes / 2 ** 30:.1f} GiB")
+    say(f"[max grid] n={n} K={K} ({K ** 3} cells); "
+        f"workspace {nf.workspace_bytes / 2 ** 30:.1f} GiB")
     bd = nf.bin(torch.from_numpy(pos).cuda())
     bd.check_status()
     _, o_off, o_perm, o_rel = oracle.bin(pos, 1.0, K)

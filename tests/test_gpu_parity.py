@@ -104,6 +104,35 @@ def test_bin_bit_exact_configs(nfmod, name):
     check_bin(nfmod, synth.config(name), name)
 
 
+def many_boxes(count):
+    rng = np.random.default_rng(31)
+    boxes = []
+    for k in range(count):
+        K = int(rng.integers(1, 7))
+        n = int(rng.integers(0, 40))
+        L = float(rng.choice([0.5, 1.0, 3.0]))
+        boxes.append(synth.Box(synth.uniform(n, 3100 + k, L), L, K, (K - 1) // 2, L / K / 50))
+    return boxes
+
+
+@pytest.mark.parametrize("count", [1000, 1100])
+def test_bin_and_forces_of_many_boxes(nfmod, count):
+    """Batches of 1000 and 1100 small boxes (0 to 39 particles, K 1..6): the
+    binning's box lookup reads the boxes' first particles from LDS up to 1024
+    boxes and searches the box table itself beyond; both are bit-exact, and the
+    forces of every particle match the oracle."""
+    boxes = many_boxes(count)
+    check_bin(nfmod, boxes, f"{count} boxes")
+    acc, _, pairs = gpu_forces(nfmod, boxes, count_pairs=True)
+    assert pairs == pair_count(boxes)
+    ref, idx = oracle_forces_boxes(boxes)
+    alone = np.linalg.norm(ref, axis=1) == 0
+    assert (acc[idx[alone]] == 0).all()
+    st = err_stats(frac_err(acc[idx[~alone]], ref[~alone]))
+    say(f"  forces {st}")
+    assert st["median"] <= MEDIAN_TOL and st["p999"] <= P999_TOL
+
+
 @pytest.mark.parametrize("label,boxes", [
     # no particle at all: every offset is 0
     ("all_empty", [synth.Box(np.zeros((0, 3), np.float32), 1.0, 5, 2, 1 / 500),

@@ -467,7 +467,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the near-field path here runs on a single MI355X "
-              "(--gpus 1); multi-GPU sharding is a design note, not a measured path.",
+              "(--gpus 1). One GPU's share of a box split into x-slabs is timed in "
+              "rows.slab_shares; runs over several GPUs are not measured here.",
               file=sys.stderr)
         sys.exit(2)
 
